@@ -1,0 +1,215 @@
+/*
+ * lj.h -- learned indexed nested loop join on MI355X (gfx950).
+ *
+ * The operation (Section II-A, "Indexed Nested Loop Joins"; Section III,
+ * "Learned Indexed Nested Loop Join"): the inner relation R is indexed by a
+ * two-level linear RMI (Section II-D, "Recursive Model Index"): a root model
+ * picks a leaf model, the leaf model predicts a position, and the leaf's
+ * min/max error bounds limit a last-mile search.  Each key of the outer
+ * relation S probes the index and every tuple of R with the same key is a
+ * match; duplicates are found by scanning the bounded range around the
+ * prediction (Section VI-B, "Duplicates").  The result is the set of pairs
+ *
+ *     { (s_idx, r_idx) : S[s_idx] == R[r_idx] }
+ *
+ * emitted in ascending (s_idx, r_idx) order, where r_idx is the position in
+ * the sorted R and s_idx the position in S as passed.
+ *
+ * Conventions for every entry point:
+ *   - Status codes are returned; nothing throws across this interface.
+ *   - Keys are uint64.  n (|R|) must be below 2^31 and m (|S|) below 2^32.
+ *   - "_dev" pointers are device memory of the index's GPU; "_host" pointers
+ *     are host memory.  Caller-owned buffers stay caller-owned.
+ *   - An index is immutable after lj_build_rmi: concurrent probes of one
+ *     index from several host threads or streams are safe.
+ *   - Work is enqueued on `stream` (0 = the null stream) of the index's
+ *     device; calls fail with LJ_ERR_ARG if another device is current.
+ */
+#ifndef LJ_H
+#define LJ_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lj_index lj_index; /* opaque, library-owned */
+
+/* One output pair (8 bytes). */
+typedef struct {
+    uint32_t s_idx;
+    uint32_t r_idx;
+} lj_pair;
+
+enum {
+    LJ_OK = 0,
+    LJ_ERR_ARG = -1,       /* null pointer, zero leaves, bad flags, wrong device */
+    LJ_ERR_UNSORTED = -2,  /* R is not non-decreasing */
+    LJ_ERR_TOO_LARGE = -3, /* n >= 2^31, m >= 2^32 or leaves > 2^26 */
+    LJ_ERR_CAPACITY = -4,  /* more pairs than out_capacity (count still set) */
+    LJ_ERR_DEVICE = -5,    /* a HIP call failed, or a kernel reported an error */
+    LJ_ERR_OOM = -6,       /* device or host allocation failed */
+    LJ_ERR_WORKSPACE = -7  /* workspace smaller than lj_probe_workspace_bytes(m) */
+};
+
+/* Leaf-model arithmetic.  Exactly one must be given to lj_build_rmi. */
+enum {
+    LJ_LEAF_FP32 = 1u, /* leaf model evaluated with fmaf on f32 parameters */
+    LJ_LEAF_FP64 = 2u  /* leaf model evaluated with fma on f64 parameters */
+};
+
+/*
+ * Build the two-level linear RMI over R (Section II-D; building happens
+ * offline and is not part of the join, Section III-A, "GRMI Building").
+ *
+ *   r_keys_host  n keys in host memory, non-decreasing (duplicates allowed).
+ *                Read only during the call; the index keeps its own device
+ *                copy of R.
+ *   n            number of keys, 0 <= n < 2^31.  n = 0 gives an index for
+ *                which every probe finds nothing.
+ *   leaves       number of leaf models, 1 <= leaves <= 2^26.
+ *   flags        LJ_LEAF_FP32 or LJ_LEAF_FP64.
+ *   stream       stream used for the uploads (the call returns after they
+ *                complete).
+ *   out_index    receives the new index; free it with lj_free_index.
+ *
+ * Fitting: the root is an FP64 least-squares line from (key - R[0]) to
+ * leaf coordinate i*leaves/n; each leaf is an FP64 least-squares line from
+ * (key - first key of the leaf) to the offset inside the leaf, rounded to
+ * f32 for LJ_LEAF_FP32.  The per-leaf min/max error bounds are then
+ * recomputed for every key of R under exactly the arithmetic the probe uses
+ * (f32 or f64), so the search window of any key of R holds all its copies.
+ *
+ * Errors: LJ_ERR_ARG, LJ_ERR_UNSORTED, LJ_ERR_TOO_LARGE, LJ_ERR_OOM,
+ * LJ_ERR_DEVICE.  On error *out_index is set to NULL.
+ */
+int lj_build_rmi(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves,
+                 uint32_t flags, hipStream_t stream, lj_index** out_index);
+
+/* Release an index and its device memory.  NULL is ignored.  The caller
+ * must ensure no probe of this index is still running on any stream. */
+void lj_free_index(lj_index* index);
+
+/*
+ * Probe the index with every key of S and emit the matching pairs
+ * (Section II-A; Section III).  Synchronous in the count: the call returns
+ * after the probe has finished on `stream`.
+ *
+ *   s_keys_dev     m outer keys in device memory (any alignment of 8).
+ *   m              number of outer keys, 0 <= m < 2^32.
+ *   out_pairs_dev  room for out_capacity pairs, or NULL when out_capacity
+ *                  is 0 (count-only probe).
+ *   out_count_host receives the total number of matching pairs.
+ *
+ * Capacity protocol (like snprintf): the pairs whose rank in the output
+ * order is below out_capacity are written; *out_count_host is always the
+ * true total; if it exceeds out_capacity the call returns LJ_ERR_CAPACITY
+ * and the caller may retry with a larger buffer.
+ *
+ * Scratch memory is taken from a per-stream cache owned by the library
+ * (grown with hipMalloc when too small).  Errors: LJ_ERR_ARG,
+ * LJ_ERR_TOO_LARGE, LJ_ERR_CAPACITY, LJ_ERR_DEVICE, LJ_ERR_OOM.
+ */
+int lj_probe_join(const lj_index* index, const uint64_t* s_keys_dev, uint64_t m,
+                  lj_pair* out_pairs_dev, uint64_t out_capacity,
+                  uint64_t* out_count_host, hipStream_t stream);
+
+/* Bytes of device workspace lj_probe_join_async needs for m outer keys. */
+uint64_t lj_probe_workspace_bytes(uint64_t m);
+
+/*
+ * Asynchronous probe: same result as lj_probe_join, but nothing is read
+ * back and nothing is allocated, so the call can be captured in a HIP graph.
+ *
+ *   out_count_dev   device uint64 that receives the total pair count, or
+ *                   UINT64_MAX if a kernel hit its internal wait bound (a
+ *                   device fault condition; the pairs are then invalid).
+ *   workspace_dev   caller-owned device scratch of at least
+ *                   lj_probe_workspace_bytes(m) bytes, 256-byte aligned;
+ *                   calls that share one workspace must be ordered on one
+ *                   stream.
+ *
+ * The capacity protocol is the same; the caller compares *out_count_dev
+ * with out_capacity after the stream completes.
+ * Errors (host-side checks only): LJ_ERR_ARG, LJ_ERR_TOO_LARGE,
+ * LJ_ERR_WORKSPACE, LJ_ERR_DEVICE (launch failure).
+ */
+int lj_probe_join_async(const lj_index* index, const uint64_t* s_keys_dev,
+                        uint64_t m, lj_pair* out_pairs_dev,
+                        uint64_t out_capacity, uint64_t* out_count_dev,
+                        void* workspace_dev, uint64_t workspace_bytes,
+                        hipStream_t stream);
+
+/* Summary of an index (sizes and model quality). */
+typedef struct {
+    uint64_t n;               /* keys in R */
+    uint32_t leaves;          /* leaf models */
+    uint32_t flags;           /* LJ_LEAF_FP32 or LJ_LEAF_FP64 */
+    uint32_t nonempty_leaves; /* leaves with at least one key */
+    uint32_t max_leaf_keys;   /* keys in the largest leaf */
+    uint64_t max_mult;        /* longest run of equal keys in R */
+    double mean_window;       /* mean search-window length over the keys of R */
+    uint64_t max_window;      /* largest search window of any leaf */
+    uint64_t device_bytes;    /* device memory held (R + leaf table) */
+    double root_a0, root_b0;  /* root model parameters */
+    uint64_t root_kmin;       /* root model key origin (R[0]) */
+} lj_index_stats;
+
+int lj_index_get_stats(const lj_index* index, lj_index_stats* out);
+
+/*
+ * Device self-check: a GPU kernel routes and predicts every key of R with
+ * the device arithmetic and counts keys whose own position falls outside
+ * their search window (0 means the host-built bounds hold on the device).
+ * Synchronous.  Errors: LJ_ERR_ARG, LJ_ERR_DEVICE, LJ_ERR_OOM.
+ */
+int lj_self_check(const lj_index* index, uint64_t* out_violations_host,
+                  hipStream_t stream);
+
+/*
+ * Window diagnostics: for each of m keys (device memory), the absolute
+ * search window [lo, hi] the probe searches (lo > hi = empty window) and
+ * the leaf chosen by the root.  Used by tests and for the model-quality
+ * statistics; not part of the join.  Asynchronous on `stream`.
+ */
+int lj_predict_windows(const lj_index* index, const uint64_t* keys_dev,
+                       uint64_t m, uint32_t* leaf_dev, int64_t* win_lo_dev,
+                       int64_t* win_hi_dev, hipStream_t stream);
+
+/*
+ * Host-side model evaluation for tests without a GPU: the same leaf choice
+ * and window as lj_predict_windows, computed on the CPU from an index's
+ * host copy of the model.
+ */
+int lj_predict_windows_host(const lj_index* index, const uint64_t* keys_host,
+                            uint64_t m, uint32_t* leaf_host,
+                            int64_t* win_lo_host, int64_t* win_hi_host);
+
+/*
+ * Build only the host-side model (no device allocation) so that the fit and
+ * its bounds can be tested without a GPU.  The index can be queried with
+ * lj_index_get_stats and lj_predict_windows_host; probing it returns
+ * LJ_ERR_ARG.  Same arguments and errors as lj_build_rmi.
+ */
+int lj_build_rmi_host_only(const uint64_t* r_keys_host, uint64_t n,
+                           uint32_t leaves, uint32_t flags,
+                           lj_index** out_index);
+
+/*
+ * Timing hook for benchmarks: the next lj_probe_join or lj_probe_join_async
+ * call made by this host thread records `start` immediately before and
+ * `stop` immediately after its probe kernel, on the call's stream.  Pass
+ * NULL events to disable.
+ */
+int lj_probe_set_timing_events(hipEvent_t start, hipEvent_t stop);
+
+/* Static description of a status code. */
+const char* lj_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LJ_H */

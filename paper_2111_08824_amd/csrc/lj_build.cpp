@@ -1,0 +1,192 @@
+// Host-side construction of the two-level linear RMI (Section II-D,
+// "Recursive Model Index"): FP64 least-squares fits of the root and of every
+// leaf, then per-leaf min/max error bounds recomputed under the exact probe
+// arithmetic of rmi_eval.h.  Building is offline and untimed (Section III-A,
+// "GRMI Building": the index exists before the join).
+#include <algorithm>
+#include <atomic>
+#include <thread>
+#include <vector>
+
+#include "lj_internal.h"
+
+namespace lj {
+namespace {
+
+// Run body(begin, end) over [0, total) split into contiguous chunks, one per
+// hardware thread.
+template <class F>
+void parallel_chunks(uint64_t total, F body) {
+    unsigned nt = std::max(1u, std::min(64u, std::thread::hardware_concurrency()));
+    if (total < (1u << 16) || nt == 1) {
+        body(0, total);
+        return;
+    }
+    std::vector<std::thread> th;
+    uint64_t step = (total + nt - 1) / nt;
+    for (unsigned t = 0; t < nt; ++t) {
+        uint64_t b = t * step, e = std::min(total, b + step);
+        if (b >= e) break;
+        th.emplace_back([=] { body(b, e); });
+    }
+    for (auto& x : th) x.join();
+}
+
+// Run body(i) for i in [0, count) with dynamic scheduling.
+template <class F>
+void parallel_items(uint64_t count, F body) {
+    unsigned nt = std::max(1u, std::min(64u, std::thread::hardware_concurrency()));
+    if (count < 64 || nt == 1) {
+        for (uint64_t i = 0; i < count; ++i) body(i);
+        return;
+    }
+    std::atomic<uint64_t> next{0};
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t)
+        th.emplace_back([&] {
+            for (;;) {
+                uint64_t b = next.fetch_add(256);
+                if (b >= count) break;
+                uint64_t e = std::min(count, b + 256);
+                for (uint64_t i = b; i < e; ++i) body(i);
+            }
+        });
+    for (auto& x : th) x.join();
+}
+
+struct Fit {
+    double slope, icpt;
+};
+
+// Least squares y = icpt + slope * x over points (x_i, y_i), centred two-pass
+// sums.  A degenerate set (all x equal) gets slope 0 and the mean of y.
+template <class X, class Y>
+Fit ols(uint64_t cnt, X x, Y y) {
+    double mx = 0, my = 0;
+    for (uint64_t i = 0; i < cnt; ++i) {
+        mx += x(i);
+        my += y(i);
+    }
+    mx /= (double)cnt;
+    my /= (double)cnt;
+    double sxx = 0, sxy = 0;
+    for (uint64_t i = 0; i < cnt; ++i) {
+        double dx = x(i) - mx;
+        sxx += dx * dx;
+        sxy += dx * (y(i) - my);
+    }
+    double b = (sxx > 0 && sxy > 0) ? sxy / sxx : 0.0;
+    return {b, my - b * mx};
+}
+
+template <class Leaf>
+void fit_leaves(const uint64_t* r, const std::vector<uint64_t>& pos0,
+                const std::vector<uint64_t>& cnt, uint32_t L, std::vector<Leaf>& out) {
+    out.assign(L, Leaf{});
+    parallel_items(L, [&](uint64_t l) {
+        Leaf lf{};
+        lf.pos0 = (uint32_t)pos0[l];
+        lf.cnt = (uint32_t)cnt[l];
+        if (cnt[l] == 0) {
+            lf.lo = 1;  // empty window marker (lo > hi); never searched
+            lf.hi = 0;
+            out[l] = lf;
+            return;
+        }
+        const uint64_t* k = r + pos0[l];
+        lf.base = k[0];
+        Fit f = ols(cnt[l], [&](uint64_t i) { return u64_to_f64(k[i] - k[0]); },
+                    [&](uint64_t i) { return (double)i; });
+        lf.slope = (decltype(lf.slope))f.slope;
+        lf.icpt = (decltype(lf.icpt))f.icpt;
+        // Error bounds under the probe's own arithmetic.
+        int64_t lo = INT64_MAX, hi = INT64_MIN;
+        for (uint64_t i = 0; i < cnt[l]; ++i) {
+            int64_t e = (int64_t)i - (int64_t)predict_rel(lf, k[i]);
+            lo = std::min(lo, e);
+            hi = std::max(hi, e);
+        }
+        lf.lo = (int32_t)lo;
+        lf.hi = (int32_t)hi;
+        out[l] = lf;
+    });
+}
+
+template <class Leaf>
+void leaf_stats(const std::vector<Leaf>& lv, lj_index* idx) {
+    double wsum = 0;
+    uint64_t wmax = 0;
+    uint32_t ne = 0, mk = 0;
+    for (const Leaf& lf : lv) {
+        if (lf.cnt == 0) continue;
+        ++ne;
+        mk = std::max(mk, lf.cnt);
+        uint64_t w = (uint64_t)((int64_t)lf.hi - (int64_t)lf.lo + 1);
+        w = std::min<uint64_t>(w, lf.cnt);
+        wsum += (double)w * lf.cnt;
+        wmax = std::max(wmax, w);
+    }
+    idx->nonempty_leaves = ne;
+    idx->max_leaf_keys = mk;
+    idx->mean_window = idx->n ? wsum / (double)idx->n : 0.0;
+    idx->max_window = wmax;
+}
+
+}  // namespace
+
+int fit_rmi(const uint64_t* r, uint64_t n, uint32_t L, uint32_t flags, lj_index* idx) {
+    idx->n = n;
+    idx->leaves = L;
+    idx->flags = flags;
+
+    // Root: least squares from (key - R[0]) to the leaf coordinate i*L/n.
+    RootModel rm{};
+    rm.leaves = L;
+    if (n > 0) {
+        rm.kmin = r[0];
+        const double scale = (double)L / (double)n;
+        Fit f = ols(n, [&](uint64_t i) { return u64_to_f64(r[i] - r[0]); },
+                    [&](uint64_t i) { return (double)i * scale; });
+        rm.a0 = f.icpt;
+        rm.b0 = f.slope;  // >= 0: keys are sorted, so the covariance is >= 0
+    }
+    idx->root = rm;
+
+    // Route every key; routing is non-decreasing in the key, so each leaf
+    // owns one contiguous run of R.
+    std::vector<uint32_t> leaf_of(n);
+    parallel_chunks(n, [&](uint64_t b, uint64_t e) {
+        for (uint64_t i = b; i < e; ++i) leaf_of[i] = route(rm, r[i]);
+    });
+    std::vector<uint64_t> pos0(L, 0), cnt(L, 0);
+    for (uint64_t i = 0; i < n; ++i) {
+        if (i > 0 && leaf_of[i] < leaf_of[i - 1]) return LJ_ERR_DEVICE;  // cannot happen
+        cnt[leaf_of[i]]++;
+    }
+    uint64_t acc = 0;
+    for (uint32_t l = 0; l < L; ++l) {
+        pos0[l] = acc;
+        acc += cnt[l];
+    }
+    leaf_of.clear();
+    leaf_of.shrink_to_fit();
+
+    // Longest run of equal keys.
+    uint64_t mm = n ? 1 : 0, run = 1;
+    for (uint64_t i = 1; i < n; ++i) {
+        run = (r[i] == r[i - 1]) ? run + 1 : 1;
+        mm = std::max(mm, run);
+    }
+    idx->max_mult = mm;
+
+    if (flags == LJ_LEAF_FP32) {
+        fit_leaves(r, pos0, cnt, L, idx->leaf32);
+        leaf_stats(idx->leaf32, idx);
+    } else {
+        fit_leaves(r, pos0, cnt, L, idx->leaf64);
+        leaf_stats(idx->leaf64, idx);
+    }
+    return LJ_OK;
+}
+
+}  // namespace lj

@@ -1,0 +1,72 @@
+// Internal definitions shared by the builder, the kernels and the C ABI.
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/lj.h"
+#include "rmi_eval.h"
+
+struct lj_index {
+    uint64_t n = 0;
+    uint32_t leaves = 0;
+    uint32_t flags = 0;
+    bool host_only = false;
+    int device = -1;
+
+    lj::RootModel root{};
+    std::vector<lj::LeafF32> leaf32;  // host copy (LJ_LEAF_FP32)
+    std::vector<lj::LeafF64> leaf64;  // host copy (LJ_LEAF_FP64)
+
+    // statistics
+    uint64_t max_mult = 0;
+    uint32_t nonempty_leaves = 0;
+    uint32_t max_leaf_keys = 0;
+    double mean_window = 0.0;
+    uint64_t max_window = 0;
+
+    // device copies
+    uint64_t* r_dev = nullptr;
+    void* leaf_dev = nullptr;
+    uint64_t device_bytes = 0;
+};
+
+namespace lj {
+
+// Fit the root and leaf models and their error bounds on the host (no HIP
+// calls).  Returns an LJ_* status.
+int fit_rmi(const uint64_t* r, uint64_t n, uint32_t leaves, uint32_t flags,
+            lj_index* idx);
+
+// Tile geometry of the fused probe kernel.
+constexpr int kBlock = 256;
+constexpr int kItems = 4;
+constexpr int kTile = kBlock * kItems;
+
+// Workspace: a 256-byte header followed by one status word per tile.
+struct WsHeader {
+    uint32_t tile_counter;  // dynamic tile ids
+    uint32_t done_counter;  // tiles finished
+    uint32_t err;           // non-zero: a wait bound was hit
+    uint32_t pad0;
+    uint64_t count;         // total pairs (internal count slot)
+};
+constexpr uint64_t kWsHeaderBytes = 256;
+
+inline uint64_t num_tiles(uint64_t m) { return (m + kTile - 1) / kTile; }
+inline uint64_t ws_bytes(uint64_t m) { return kWsHeaderBytes + num_tiles(m) * 8; }
+
+// Kernel launchers (lj_kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m,
+                        lj_pair* out, uint64_t cap, uint64_t* count_dev,
+                        void* ws, hipStream_t stream, hipEvent_t ev0,
+                        hipEvent_t ev1);
+hipError_t launch_set_u64(uint64_t* p, uint64_t v, hipStream_t stream);
+hipError_t launch_self_check(const lj_index* idx, uint64_t* violations_dev,
+                             hipStream_t stream);
+hipError_t launch_predict_windows(const lj_index* idx, const uint64_t* keys,
+                                  uint64_t m, uint32_t* leaf, int64_t* wlo,
+                                  int64_t* whi, hipStream_t stream);
+
+}  // namespace lj

@@ -1,0 +1,513 @@
+// GPU kernels of the learned indexed nested loop join probe (gfx950).
+//
+// One fused kernel runs the whole probe for a tile of outer keys
+// (Section II-A: scan S, use the index on R to fetch the tuples with the same
+// key; Section II-D: root model -> leaf model -> bounded last-mile search;
+// Section VI-B, "Duplicates": range scan of equal keys inside the bounds):
+//
+//   1. coalesced read of the tile's S keys (lane t of the block handles keys
+//      t, t+256, t+512, t+768 of the tile);
+//   2. root model (FP64 fma) -> leaf record (32 or 48 bytes, read through
+//      L2/MALL) -> leaf model (FP32 fmaf or FP64 fma) -> window [lo, hi];
+//   3. lower_bound in R over the window, the kItems keys of a lane advanced
+//      in lockstep so that each lane keeps kItems independent loads in flight;
+//      the element found is the last one read with R[mid] >= x, so the
+//      equality test needs no extra load;
+//   4. length of the run of equal keys (only when R has duplicates);
+//   5. tile-local exclusive offsets of the outputs: ballot/popcount per wave
+//      when every count is 0 or 1, an LDS scan otherwise;
+//   6. global offset of the tile by a single-pass decoupled look-back over the
+//      tiles' status words (Merrill and Garland, "Single-pass parallel prefix
+//      scan with decoupled look-back", NVIDIA TR 2016), tile ids handed out
+//      by an atomic counter so that every predecessor of a waiting tile is
+//      already running;
+//   7. pair emission in (s_idx, r_idx) order: one store per match when every
+//      count is 0 or 1, otherwise a load-balanced loop in which each output
+//      slot finds its key by binary search over the LDS offsets, so stores
+//      stay contiguous for any run length.
+//
+// No S key, count or offset makes a round trip through HBM between the
+// steps: the only traffic is S, the R lines and leaf records the searches
+// touch, the pairs, and 8 bytes of status per tile.
+#include <hip/hip_runtime.h>
+
+#include "lj_internal.h"
+
+namespace lj {
+namespace {
+
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagInc = 2ull << 62;
+constexpr uint64_t kValMask = (1ull << 62) - 1;
+constexpr uint32_t kSpinLimit = 1u << 24;  // ~0.5 s of s_sleep before giving up
+
+struct ProbeParams {
+    const uint64_t* r;
+    const void* leaves;
+    RootModel root;
+    const uint64_t* s;
+    uint64_t m;
+    lj_pair* out;
+    uint64_t cap;
+    uint64_t* count_out;
+    WsHeader* hdr;
+    uint64_t* status;
+    uint32_t ntiles;
+};
+
+__device__ inline uint64_t ld_status(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_status(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline uint64_t wave_sum(uint64_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+__device__ inline uint64_t wave_incl_scan(uint64_t v, int lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint64_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Leaf records are read as whole 16-byte vectors.
+__device__ inline LeafF32 load_leaf(const LeafF32* p) {
+    const uint4* q = (const uint4*)p;
+    uint4 a = q[0], b = q[1];
+    LeafF32 l;
+    l.base = (uint64_t)a.x | ((uint64_t)a.y << 32);
+    l.slope = __uint_as_float(a.z);
+    l.icpt = __uint_as_float(a.w);
+    l.pos0 = b.x;
+    l.cnt = b.y;
+    l.lo = (int32_t)b.z;
+    l.hi = (int32_t)b.w;
+    return l;
+}
+
+__device__ inline LeafF64 load_leaf(const LeafF64* p) {
+    const uint4* q = (const uint4*)p;
+    uint4 a = q[0], b = q[1], c = q[2];
+    LeafF64 l;
+    l.base = (uint64_t)a.x | ((uint64_t)a.y << 32);
+    l.slope = __hiloint2double((int)a.w, (int)a.z);
+    l.icpt = __hiloint2double((int)b.y, (int)b.x);
+    l.pos0 = b.z;
+    l.cnt = b.w;
+    l.lo = (int32_t)c.x;
+    l.hi = (int32_t)c.y;
+    l.pad = 0;
+    return l;
+}
+
+// Decoupled look-back, run by wave 0 of the block.  Publishes the tile's
+// aggregate, accumulates the predecessors' values until one with an
+// inclusive prefix is found, publishes the tile's inclusive prefix and
+// returns its exclusive prefix (valid in every lane of wave 0).
+__device__ uint64_t look_back(uint64_t* status, uint32_t tile, uint64_t total,
+                              uint32_t* err, int lane) {
+    if (tile == 0) {
+        if (lane == 0) st_status(&status[0], kFlagInc | total);
+        return 0;
+    }
+    if (lane == 0) st_status(&status[tile], kFlagAgg | total);
+    uint64_t excl = 0;
+    int64_t base = (int64_t)tile - 1;
+    for (;;) {
+        int64_t idx = base - lane;
+        uint64_t st = idx >= 0 ? ld_status(&status[idx]) : kFlagInc;
+        uint32_t spins = 0;
+        while (__ballot((st >> 62) == 0)) {
+            if ((st >> 62) == 0) st = ld_status(&status[idx]);
+            if (++spins > kSpinLimit) {
+                // A predecessor never published: report and stop waiting so
+                // that the kernel still exits.
+                if ((st >> 62) == 0) {
+                    atomicOr(err, 1u);
+                    st = kFlagInc;
+                }
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        uint64_t inc = __ballot((st >> 62) == 2);
+        if (inc) {
+            int first = __ffsll((unsigned long long)inc) - 1;
+            excl += wave_sum(lane <= first ? (st & kValMask) : 0);
+            break;
+        }
+        excl += wave_sum(st & kValMask);
+        base -= 64;
+    }
+    if (lane == 0) st_status(&status[tile], kFlagInc | (excl + total));
+    return excl;
+}
+
+// Last tile to finish writes the total (or UINT64_MAX after a wait error).
+__device__ void finish_tile(const ProbeParams& p) {
+    if (threadIdx.x == 0) {
+        __threadfence();
+        uint32_t done = atomicAdd(&p.hdr->done_counter, 1u);
+        if (done == p.ntiles - 1) {
+            __threadfence();
+            uint32_t e = __hip_atomic_load(&p.hdr->err, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t tot = ld_status(&p.status[p.ntiles - 1]) & kValMask;
+            *p.count_out = e ? ~0ull : tot;
+        }
+    }
+}
+
+template <class Leaf, bool kUnique>
+__global__ __launch_bounds__(kBlock) void probe_join_kernel(ProbeParams p) {
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_excl;
+    __shared__ uint64_t s_wsum[kItems * (kBlock / 64)];
+    __shared__ uint64_t s_off[kUnique ? 1 : kTile + 1];
+    __shared__ uint32_t s_j0[kUnique ? 1 : kTile];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+
+    if (tid == 0) s_tile = atomicAdd(&p.hdr->tile_counter, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint64_t tbase = (uint64_t)tile * kTile;
+    const Leaf* leaves = (const Leaf*)p.leaves;
+    const uint64_t* __restrict__ R = p.r;
+
+    uint64_t x[kItems];
+    uint32_t first[kItems], len[kItems], end[kItems];
+    uint64_t gev[kItems];
+    bool valid[kItems];
+
+    // 1: keys.  Loads are unconditional (clamped index) so that the four
+    // loads of a lane are in flight together.
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        uint64_t s = tbase + (uint64_t)k * kBlock + tid;
+        valid[k] = s < p.m;
+        x[k] = p.s[valid[k] ? s : p.m - 1];
+    }
+    // 2: root model, leaf record, leaf model, window.
+    Leaf lf[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) lf[k] = load_leaf(leaves + route(p.root, x[k]));
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        int64_t rel = predict_rel(lf[k], x[k]);
+        int64_t wlo = rel + lf[k].lo, whi = rel + lf[k].hi;
+        if (wlo < 0) wlo = 0;
+        if (whi > (int64_t)lf[k].cnt - 1) whi = (int64_t)lf[k].cnt - 1;
+        const bool live = valid[k] && lf[k].cnt != 0 && wlo <= whi;
+        first[k] = live ? lf[k].pos0 + (uint32_t)wlo : 0;
+        len[k] = live ? (uint32_t)(whi - wlo + 1) : 0;
+        end[k] = live ? lf[k].pos0 + (uint32_t)whi + 1 : 0;
+        gev[k] = 0;
+    }
+
+    // 3: lockstep lower_bound over the windows.  Finished keys re-read R[0]
+    // (a cached line) so that the loop body has no branches and the loads of
+    // the kItems keys issue back to back.
+    for (;;) {
+        uint32_t anylen = 0;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) anylen |= len[k];
+        if (!anylen) break;
+        uint64_t v[kItems];
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) v[k] = R[len[k] ? first[k] + (len[k] >> 1) : 0];
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const uint32_t half = len[k] >> 1;
+            const bool act = len[k] != 0;
+            const bool lt = v[k] < x[k];
+            first[k] = (act && lt) ? first[k] + half + 1 : first[k];
+            gev[k] = (act && !lt) ? v[k] : gev[k];
+            len[k] = act ? (lt ? len[k] - half - 1 : half) : 0;
+        }
+    }
+
+    // 4: run lengths.  first[k] < end[k] means R[first[k]] == gev[k] >= x[k].
+    uint32_t c[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) c[k] = (first[k] < end[k] && gev[k] == x[k]) ? 1u : 0u;
+    if (!kUnique) {
+        // Forward scan of equal keys, four at a time, bounded by the window.
+        uint32_t cur[kItems];
+        bool act[kItems];
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            cur[k] = first[k] + 1;
+            act[k] = c[k] && cur[k] < end[k];
+        }
+        for (;;) {
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < kItems; ++k) any |= act[k];
+            if (!any) break;
+            uint64_t v[kItems][4];
+#pragma unroll
+            for (int k = 0; k < kItems; ++k)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool in = act[k] && cur[k] + u < end[k];
+                    v[k][u] = R[in ? cur[k] + u : 0];
+                    if (!in) v[k][u] = ~x[k];
+                }
+#pragma unroll
+            for (int k = 0; k < kItems; ++k) {
+                bool run = act[k];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    run = run && v[k][u] == x[k];
+                    c[k] += run ? 1u : 0u;
+                }
+                cur[k] += 4;
+                act[k] = run && cur[k] < end[k];
+            }
+        }
+    }
+
+    if (kUnique) {
+        // 5: ballot/popcount offsets; key order in the tile is (k, wave, lane).
+        uint32_t lane_off[kItems];
+        const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            uint64_t mask = __ballot(c[k] != 0);
+            lane_off[k] = (uint32_t)__popcll(mask & lt);
+            if (lane == 0) s_wsum[k * (kBlock / 64) + wave] = (uint64_t)__popcll(mask);
+        }
+        __syncthreads();
+        uint64_t total = 0;
+#pragma unroll
+        for (int q = 0; q < kItems * (kBlock / 64); ++q) total += s_wsum[q];
+        // 6: look-back.
+        if (wave == 0) {
+            uint64_t e = look_back(p.status, tile, total, &p.hdr->err, lane);
+            if (lane == 0) s_excl = e;
+        }
+        __syncthreads();
+        const uint64_t excl = s_excl;
+        // 7: one store per match.
+        if (p.out) {
+            uint64_t pre = 0;
+#pragma unroll
+            for (int k = 0; k < kItems; ++k) {
+                uint64_t wpre = 0;
+                for (int w = 0; w < wave; ++w) wpre += s_wsum[k * (kBlock / 64) + w];
+                uint64_t pos = excl + pre + wpre + lane_off[k];
+                if (c[k] && pos < p.cap) {
+                    lj_pair pr;
+                    pr.s_idx = (uint32_t)(tbase + (uint64_t)k * kBlock + tid);
+                    pr.r_idx = first[k];
+                    p.out[pos] = pr;
+                }
+#pragma unroll
+                for (int w = 0; w < kBlock / 64; ++w) pre += s_wsum[k * (kBlock / 64) + w];
+            }
+        }
+    } else {
+        // 5: LDS scan of the counts in tile order.
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            int q = k * kBlock + tid;
+            s_off[q] = c[k];
+            s_j0[q] = first[k];
+        }
+        __syncthreads();
+        uint64_t loc[kItems];
+        uint64_t tsum = 0;
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            loc[i] = tsum;
+            tsum += s_off[tid * kItems + i];
+        }
+        uint64_t incl = wave_incl_scan(tsum, lane);
+        if (lane == 63) s_wsum[wave] = incl;
+        __syncthreads();
+        uint64_t wpre = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) {
+            if (w < wave) wpre += s_wsum[w];
+            total += s_wsum[w];
+        }
+        const uint64_t texcl = wpre + incl - tsum;
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) s_off[tid * kItems + i] = texcl + loc[i];
+        if (tid == 0) s_off[kTile] = total;
+        // 6: look-back.
+        if (wave == 0) {
+            uint64_t e = look_back(p.status, tile, total, &p.hdr->err, lane);
+            if (lane == 0) s_excl = e;
+        }
+        __syncthreads();
+        const uint64_t excl = s_excl;
+        // 7: load-balanced emission of the tile's outputs.
+        if (p.out && excl < p.cap) {
+            uint64_t limit = p.cap - excl < total ? p.cap - excl : total;
+            for (uint64_t o = tid; o < limit; o += kBlock) {
+                // last q with s_off[q] <= o
+                int lo = 0, hi = kTile;  // s_off[kTile] = total > o
+                while (hi - lo > 1) {
+                    int mid = (lo + hi) >> 1;
+                    if (s_off[mid] <= o) lo = mid;
+                    else hi = mid;
+                }
+                lj_pair pr;
+                pr.s_idx = (uint32_t)(tbase + (uint64_t)lo);
+                pr.r_idx = s_j0[lo] + (uint32_t)(o - s_off[lo]);
+                p.out[excl + o] = pr;
+            }
+        }
+    }
+    finish_tile(p);
+}
+
+__global__ void zero_words(uint64_t* w, uint64_t nwords) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        w[i] = 0;
+}
+
+__global__ void set_u64_kernel(uint64_t* p, uint64_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+template <class Leaf>
+__global__ void self_check_kernel(const uint64_t* R, uint64_t n, const Leaf* leaves,
+                                  RootModel root, unsigned long long* viol) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t x = R[i];
+        const Leaf lf = leaves[route(root, x)];
+        bool ok = lf.cnt != 0 && i >= lf.pos0 && i < (uint64_t)lf.pos0 + lf.cnt;
+        if (ok) {
+            int64_t e = (int64_t)(i - lf.pos0) - predict_rel(lf, x);
+            ok = e >= lf.lo && e <= lf.hi;
+        }
+        if (!ok) atomicAdd(viol, 1ull);
+    }
+}
+
+template <class Leaf>
+__global__ void predict_windows_kernel(const uint64_t* keys, uint64_t m, const Leaf* leaves,
+                                       RootModel root, uint32_t* leaf_out, int64_t* wlo,
+                                       int64_t* whi) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t x = keys[i];
+        uint32_t l = route(root, x);
+        const Leaf lf = leaves[l];
+        int64_t lo = 1, hi = 0;
+        if (lf.cnt != 0) {
+            int64_t rel = predict_rel(lf, x);
+            int64_t a = rel + lf.lo, b = rel + lf.hi;
+            if (a < 0) a = 0;
+            if (b > (int64_t)lf.cnt - 1) b = (int64_t)lf.cnt - 1;
+            if (a <= b) {
+                lo = (int64_t)lf.pos0 + a;
+                hi = (int64_t)lf.pos0 + b;
+            }
+        }
+        if (leaf_out) leaf_out[i] = l;
+        if (wlo) wlo[i] = lo;
+        if (whi) whi[i] = hi;
+    }
+}
+
+unsigned grid_for(uint64_t work, unsigned block) {
+    uint64_t g = (work + block - 1) / block;
+    if (g > 65536) g = 65536;
+    return (unsigned)(g ? g : 1);
+}
+
+}  // namespace
+
+hipError_t launch_set_u64(uint64_t* p, uint64_t v, hipStream_t stream) {
+    hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(64), 0, stream, p, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m, lj_pair* out,
+                        uint64_t cap, uint64_t* count_dev, void* ws, hipStream_t stream,
+                        hipEvent_t ev0, hipEvent_t ev1) {
+    const uint64_t nt = num_tiles(m);
+    const uint64_t words = ws_bytes(m) / 8;
+    hipLaunchKernelGGL(zero_words, dim3(grid_for(words, 256)), dim3(256), 0, stream,
+                       (uint64_t*)ws, words);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+
+    ProbeParams p;
+    p.r = idx->r_dev;
+    p.leaves = idx->leaf_dev;
+    p.root = idx->root;
+    p.s = s;
+    p.m = m;
+    p.out = out;
+    p.cap = out ? cap : 0;
+    p.count_out = count_dev;
+    p.hdr = (WsHeader*)ws;
+    p.status = (uint64_t*)((char*)ws + kWsHeaderBytes);
+    p.ntiles = (uint32_t)nt;
+
+    const bool uniq = idx->max_mult <= 1;
+    const bool f32 = idx->flags == LJ_LEAF_FP32;
+    if (ev0) {
+        e = hipEventRecord(ev0, stream);
+        if (e != hipSuccess) return e;
+    }
+    dim3 grid((unsigned)nt), block(kBlock);
+    if (f32 && uniq)
+        hipLaunchKernelGGL((probe_join_kernel<LeafF32, true>), grid, block, 0, stream, p);
+    else if (f32)
+        hipLaunchKernelGGL((probe_join_kernel<LeafF32, false>), grid, block, 0, stream, p);
+    else if (uniq)
+        hipLaunchKernelGGL((probe_join_kernel<LeafF64, true>), grid, block, 0, stream, p);
+    else
+        hipLaunchKernelGGL((probe_join_kernel<LeafF64, false>), grid, block, 0, stream, p);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ev1) e = hipEventRecord(ev1, stream);
+    return e;
+}
+
+hipError_t launch_self_check(const lj_index* idx, uint64_t* viol, hipStream_t stream) {
+    hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, stream, viol, (uint64_t)1);
+    unsigned g = grid_for(idx->n, 256);
+    if (idx->n == 0) return hipGetLastError();
+    if (idx->flags == LJ_LEAF_FP32)
+        hipLaunchKernelGGL(self_check_kernel<LeafF32>, dim3(g), dim3(256), 0, stream,
+                           idx->r_dev, idx->n, (const LeafF32*)idx->leaf_dev, idx->root,
+                           (unsigned long long*)viol);
+    else
+        hipLaunchKernelGGL(self_check_kernel<LeafF64>, dim3(g), dim3(256), 0, stream,
+                           idx->r_dev, idx->n, (const LeafF64*)idx->leaf_dev, idx->root,
+                           (unsigned long long*)viol);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict_windows(const lj_index* idx, const uint64_t* keys, uint64_t m,
+                                  uint32_t* leaf, int64_t* wlo, int64_t* whi,
+                                  hipStream_t stream) {
+    if (m == 0) return hipSuccess;
+    unsigned g = grid_for(m, 256);
+    if (idx->flags == LJ_LEAF_FP32)
+        hipLaunchKernelGGL(predict_windows_kernel<LeafF32>, dim3(g), dim3(256), 0, stream,
+                           keys, m, (const LeafF32*)idx->leaf_dev, idx->root, leaf, wlo, whi);
+    else
+        hipLaunchKernelGGL(predict_windows_kernel<LeafF64>, dim3(g), dim3(256), 0, stream,
+                           keys, m, (const LeafF64*)idx->leaf_dev, idx->root, leaf, wlo, whi);
+    return hipGetLastError();
+}
+
+}  // namespace lj

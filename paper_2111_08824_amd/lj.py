@@ -1,0 +1,260 @@
+"""Python binding of the C ABI in include/lj.h (argument marshalling only).
+
+Every step of the probe runs in the HIP kernels of liblj.so; this module only
+converts numpy arrays and torch tensors to pointers and sizes.  It fails
+loudly when liblj.so has not been built: there is no fallback path.
+
+Memory conventions: R is passed as a host numpy array (the index uploads its
+own copy); S, the output pairs and device counters are torch CUDA tensors,
+with uint64 keys carried in int64 tensors (bit-identical storage).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblj.so")
+
+LJ_OK = 0
+LJ_ERR_ARG = -1
+LJ_ERR_UNSORTED = -2
+LJ_ERR_TOO_LARGE = -3
+LJ_ERR_CAPACITY = -4
+LJ_ERR_DEVICE = -5
+LJ_ERR_OOM = -6
+LJ_ERR_WORKSPACE = -7
+
+LJ_LEAF_FP32 = 1
+LJ_LEAF_FP64 = 2
+
+EXPORTED = (
+    "lj_build_rmi", "lj_free_index", "lj_probe_join", "lj_probe_workspace_bytes",
+    "lj_probe_join_async", "lj_index_get_stats", "lj_self_check", "lj_predict_windows",
+    "lj_predict_windows_host", "lj_build_rmi_host_only", "lj_probe_set_timing_events",
+    "lj_strerror",
+)
+
+
+class LJError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+
+
+class lj_index_stats(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_uint64),
+        ("leaves", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+        ("nonempty_leaves", ctypes.c_uint32),
+        ("max_leaf_keys", ctypes.c_uint32),
+        ("max_mult", ctypes.c_uint64),
+        ("mean_window", ctypes.c_double),
+        ("max_window", ctypes.c_uint64),
+        ("device_bytes", ctypes.c_uint64),
+        ("root_a0", ctypes.c_double),
+        ("root_b0", ctypes.c_double),
+        ("root_kmin", ctypes.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load liblj.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -m paper_2111_08824_amd.build` (no fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+        L.lj_build_rmi.argtypes = [vp, u64, u32, u32, vp, ctypes.POINTER(vp)]
+        L.lj_build_rmi_host_only.argtypes = [vp, u64, u32, u32, ctypes.POINTER(vp)]
+        L.lj_free_index.argtypes = [vp]
+        L.lj_free_index.restype = None
+        L.lj_probe_join.argtypes = [vp, vp, u64, vp, u64, ctypes.POINTER(u64), vp]
+        L.lj_probe_workspace_bytes.argtypes = [u64]
+        L.lj_probe_workspace_bytes.restype = u64
+        L.lj_probe_join_async.argtypes = [vp, vp, u64, vp, u64, vp, vp, u64, vp]
+        L.lj_index_get_stats.argtypes = [vp, ctypes.POINTER(lj_index_stats)]
+        L.lj_self_check.argtypes = [vp, ctypes.POINTER(u64), vp]
+        L.lj_predict_windows.argtypes = [vp, vp, u64, vp, vp, vp, vp]
+        L.lj_predict_windows_host.argtypes = [vp, vp, u64, vp, vp, vp]
+        L.lj_probe_set_timing_events.argtypes = [vp, vp]
+        L.lj_strerror.argtypes = [i32]
+        L.lj_strerror.restype = ctypes.c_char_p
+        for f in ("lj_build_rmi", "lj_build_rmi_host_only", "lj_probe_join",
+                  "lj_probe_join_async", "lj_index_get_stats", "lj_self_check",
+                  "lj_predict_windows", "lj_predict_windows_host",
+                  "lj_probe_set_timing_events"):
+            getattr(L, f).restype = i32
+        _lib = L
+    return _lib
+
+
+def strerror(status: int) -> str:
+    return lib().lj_strerror(int(status)).decode()
+
+
+def _check(status: int, what: str) -> int:
+    if status != LJ_OK:
+        raise LJError(status, what)
+    return status
+
+
+def _stream_ptr(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dev_ptr(t) -> int:
+    if t is None:
+        return 0
+    assert t.is_cuda and t.is_contiguous()
+    return t.data_ptr()
+
+
+def _host_u64(a) -> np.ndarray:
+    a = np.ascontiguousarray(a)
+    if a.dtype != np.uint64:
+        a = a.astype(np.uint64)
+    return a
+
+
+class Index:
+    """Owner of an lj_index handle."""
+
+    def __init__(self, handle: int, host_only: bool):
+        self.handle = handle
+        self.host_only = host_only
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().lj_free_index(self.handle)
+            self.handle = None
+
+    @property
+    def stats(self) -> lj_index_stats:
+        st = lj_index_stats()
+        _check(lib().lj_index_get_stats(self.handle, ctypes.byref(st)), "lj_index_get_stats")
+        return st
+
+
+def lj_build_rmi(r_keys, leaves: int, flags: int = LJ_LEAF_FP32, stream=None) -> Index:
+    """Build the index over host array r_keys (sorted uint64)."""
+    R = _host_u64(r_keys)
+    h = ctypes.c_void_p()
+    _check(lib().lj_build_rmi(R.ctypes.data if len(R) else None, len(R), leaves, flags,
+                              _stream_ptr(stream), ctypes.byref(h)), "lj_build_rmi")
+    return Index(h.value, False)
+
+
+def lj_build_rmi_host_only(r_keys, leaves: int, flags: int = LJ_LEAF_FP32) -> Index:
+    R = _host_u64(r_keys)
+    h = ctypes.c_void_p()
+    _check(lib().lj_build_rmi_host_only(R.ctypes.data if len(R) else None, len(R), leaves,
+                                        flags, ctypes.byref(h)), "lj_build_rmi_host_only")
+    return Index(h.value, True)
+
+
+def lj_probe_join(index: Index, s_keys_dev, out_pairs_dev=None, stream=None):
+    """Probe with device tensor s_keys_dev (int64 storage of uint64 keys).
+
+    out_pairs_dev: int32 tensor of shape (cap, 2) or None (count only).
+    Returns (status, count); status is LJ_OK or LJ_ERR_CAPACITY.
+    """
+    m = s_keys_dev.numel()
+    cap = 0 if out_pairs_dev is None else out_pairs_dev.shape[0]
+    cnt = ctypes.c_uint64()
+    st = lib().lj_probe_join(index.handle, _dev_ptr(s_keys_dev) if m else None, m,
+                             _dev_ptr(out_pairs_dev) if cap else None, cap,
+                             ctypes.byref(cnt), _stream_ptr(stream))
+    if st not in (LJ_OK, LJ_ERR_CAPACITY):
+        raise LJError(st, "lj_probe_join")
+    return st, cnt.value
+
+
+def lj_probe_workspace_bytes(m: int) -> int:
+    return int(lib().lj_probe_workspace_bytes(m))
+
+
+def lj_probe_join_async(index: Index, s_keys_dev, out_pairs_dev, count_dev, workspace_dev,
+                        stream=None) -> None:
+    """Enqueue a probe; count_dev is a device int64 tensor of one element."""
+    m = s_keys_dev.numel()
+    cap = 0 if out_pairs_dev is None else out_pairs_dev.shape[0]
+    ws_bytes = 0 if workspace_dev is None else workspace_dev.numel() * workspace_dev.element_size()
+    _check(lib().lj_probe_join_async(index.handle, _dev_ptr(s_keys_dev) if m else None, m,
+                                     _dev_ptr(out_pairs_dev) if cap else None, cap,
+                                     _dev_ptr(count_dev), _dev_ptr(workspace_dev), ws_bytes,
+                                     _stream_ptr(stream)), "lj_probe_join_async")
+
+
+def lj_self_check(index: Index, stream=None) -> int:
+    v = ctypes.c_uint64()
+    _check(lib().lj_self_check(index.handle, ctypes.byref(v), _stream_ptr(stream)),
+           "lj_self_check")
+    return v.value
+
+
+def lj_predict_windows(index: Index, keys_dev, leaf_dev, lo_dev, hi_dev, stream=None) -> None:
+    _check(lib().lj_predict_windows(index.handle, _dev_ptr(keys_dev), keys_dev.numel(),
+                                    _dev_ptr(leaf_dev), _dev_ptr(lo_dev), _dev_ptr(hi_dev),
+                                    _stream_ptr(stream)), "lj_predict_windows")
+
+
+def lj_predict_windows_host(index: Index, keys):
+    keys = _host_u64(keys)
+    m = len(keys)
+    leaf = np.empty(m, dtype=np.uint32)
+    lo = np.empty(m, dtype=np.int64)
+    hi = np.empty(m, dtype=np.int64)
+    _check(lib().lj_predict_windows_host(index.handle, keys.ctypes.data if m else None, m,
+                                         leaf.ctypes.data, lo.ctypes.data, hi.ctypes.data),
+           "lj_predict_windows_host")
+    return leaf, lo, hi
+
+
+def lj_probe_set_timing_events(start, stop) -> None:
+    """start/stop: torch.cuda.Event objects (or None to disable)."""
+    _check(lib().lj_probe_set_timing_events(
+        start.cuda_event if start is not None else None,
+        stop.cuda_event if stop is not None else None), "lj_probe_set_timing_events")
+
+
+# ---------------------------------------------------------------------------
+# Convenience wrappers used by tests and the benchmark.
+
+def to_device_keys(a: np.ndarray, device="cuda"):
+    """uint64 numpy array -> int64 CUDA tensor with the same bits."""
+    import torch
+    a = _host_u64(a)
+    return torch.from_numpy(a.view(np.int64)).to(device)
+
+
+def probe(index: Index, s_keys_dev, capacity: int | None = None, stream=None):
+    """Probe and return the pairs as an (count, 2) int32 CUDA tensor.
+
+    With capacity None, a count-only probe sizes the output first."""
+    import torch
+    if capacity is None:
+        _, capacity = lj_probe_join(index, s_keys_dev, None, stream)
+    out = torch.empty((max(capacity, 1), 2), dtype=torch.int32, device=s_keys_dev.device)
+    st, cnt = lj_probe_join(index, s_keys_dev, out[:capacity] if capacity else None, stream)
+    if st == LJ_ERR_CAPACITY:
+        out = torch.empty((cnt, 2), dtype=torch.int32, device=s_keys_dev.device)
+        st, cnt = lj_probe_join(index, s_keys_dev, out, stream)
+        _check(st, "lj_probe_join")
+    return out[:cnt]

@@ -1,0 +1,177 @@
+"""GPU parity: the HIP probe against the CPU oracle, bit-exact.
+
+Every case builds the index through the C ABI, probes on the GPU and compares
+the (s_idx, r_idx) pairs element by element with the oracle's sort-merge join
+on the same seeded inputs (join output is integer index work: the bar is
+exact equality, in the canonical (s_idx, r_idx) order).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from paper_2111_08824_amd import lj
+
+pytestmark = pytest.mark.gpu
+
+U64MAX = 2**64 - 1
+FLAGS = [lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP64]
+
+
+def gpu_join(R, S, leaves, flags, capacity=None):
+    ix = lj.lj_build_rmi(np.asarray(R, dtype=np.uint64), leaves, flags)
+    s = lj.to_device_keys(np.asarray(S, dtype=np.uint64))
+    pairs = lj.probe(ix, s, capacity)
+    out = pairs.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    return ix, out
+
+
+def assert_parity(R, S, leaves, flags, label=""):
+    print(f"[parity] {label} n={len(R)} m={len(S)} leaves={leaves} flags={flags}", flush=True)
+    ix, got = gpu_join(R, S, leaves, flags)
+    want = oracle.sort_merge_join(R, S)
+    assert got.shape == want.shape, (got.shape, want.shape)
+    assert np.array_equal(got, want)
+    assert lj.lj_self_check(ix) == 0
+    return got
+
+
+@pytest.mark.parametrize("flags", FLAGS)
+def test_uniform_1m(flags):
+    w = workloads.c1_uniform()
+    got = assert_parity(w.R, w.S, w.leaves, flags, w.name)
+    assert len(got) == w.expected_count == 500_000
+
+
+@pytest.mark.parametrize("flags", FLAGS)
+def test_lognormal_zipf_2m(flags):
+    w = workloads.c2_lognormal_zipf(scale=0.01)
+    got = assert_parity(w.R, w.S, w.leaves, flags, w.name)
+    assert len(got) == w.expected_count
+
+
+@pytest.mark.parametrize("flags", FLAGS)
+def test_dup_runs_1m(flags):
+    w = workloads.c3_dup_runs(scale=0.01)
+    assert_parity(w.R, w.S, w.leaves, flags, w.name)
+
+
+@pytest.mark.parametrize("m", [1, 2, 63, 64, 255, 1023, 1024, 1025, 4096 + 7, 77_777])
+def test_ragged_tile_tails(m):
+    R = workloads.gen.uniform_unique(50_000, 20, 3)
+    S = workloads.gen.probe_mix(R, m, 0.6, 4, miss_hi=2**20)
+    assert_parity(R, S, 256, lj.LJ_LEAF_FP32, f"tail m={m}")
+
+
+@pytest.mark.parametrize("leaves", [1, 2, 1000, 200_003])
+def test_leaf_counts(leaves):
+    R = workloads.gen.lognormal_unique(50_000, 2.0, 5)
+    S = workloads.gen.probe_mix(R, 60_000, 0.5, 6, miss_hi=2**63)
+    assert_parity(R, S, leaves, lj.LJ_LEAF_FP32, f"leaves={leaves}")
+
+
+def test_heavy_duplicates_load_balanced_emission():
+    # One key repeated 5000 times in R and 3 times in S, other keys around it.
+    R = np.concatenate([np.arange(0, 100, dtype=np.uint64),
+                        np.full(5000, 1000, dtype=np.uint64),
+                        np.arange(2000, 2100, dtype=np.uint64)])
+    S = np.array([1000, 5, 1000, 7000, 2050, 1000], dtype=np.uint64)
+    got = assert_parity(R, S, 8, lj.LJ_LEAF_FP32, "heavy duplicates")
+    assert len(got) == 3 * 5000 + 2
+
+
+def test_all_equal_inner_relation():
+    R = np.full(3000, 42, dtype=np.uint64)
+    S = np.array([42, 41, 43, 42], dtype=np.uint64)
+    got = assert_parity(R, S, 16, lj.LJ_LEAF_FP64, "all equal")
+    assert len(got) == 6000
+
+
+def test_extreme_keys():
+    R = np.array([0, 0, 1, 2**63, U64MAX - 1, U64MAX, U64MAX], dtype=np.uint64)
+    S = np.array([U64MAX, 0, 7, 2**63, U64MAX - 2, 1, U64MAX], dtype=np.uint64)
+    for flags in FLAGS:
+        assert_parity(R, S, 3, flags, "extreme keys")
+
+
+def test_all_misses_and_empty_inputs():
+    R = workloads.gen.uniform_unique(10_000, 30, 8)
+    S = np.array([2**40 + i for i in range(5000)], dtype=np.uint64)
+    got = assert_parity(R, S, 64, lj.LJ_LEAF_FP32, "all misses")
+    assert len(got) == 0
+    # m = 0
+    ix = lj.lj_build_rmi(R, 64)
+    s0 = lj.to_device_keys(np.empty(0, dtype=np.uint64))
+    assert lj.lj_probe_join(ix, s0) == (lj.LJ_OK, 0)
+    # n = 0
+    ix0 = lj.lj_build_rmi(np.empty(0, dtype=np.uint64), 4)
+    s = lj.to_device_keys(np.array([0, 1, U64MAX], dtype=np.uint64))
+    assert lj.lj_probe_join(ix0, s) == (lj.LJ_OK, 0)
+
+
+def test_capacity_protocol():
+    import torch
+    w = workloads.c3_dup_runs(scale=0.001)
+    want = oracle.sort_merge_join(w.R, w.S)
+    ix = lj.lj_build_rmi(w.R, w.leaves)
+    s = lj.to_device_keys(w.S)
+    st, cnt = lj.lj_probe_join(ix, s, None)  # count only
+    assert (st, cnt) == (lj.LJ_OK, len(want))
+    cap = len(want) // 3
+    out = torch.full((cap, 2), -1, dtype=torch.int32, device="cuda")
+    st, cnt = lj.lj_probe_join(ix, s, out)
+    assert st == lj.LJ_ERR_CAPACITY and cnt == len(want)
+    got = out.cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, want[:cap])  # the first cap pairs, in order
+
+
+def test_split_invariance():
+    w = workloads.c2_lognormal_zipf(scale=0.005)
+    ix = lj.lj_build_rmi(w.R, w.leaves)
+    whole = lj.probe(ix, lj.to_device_keys(w.S)).cpu().numpy().view(np.uint32)
+    parts = []
+    cuts = [0, 1, 1000, 1024 * 7 + 3, 400_000, len(w.S)]
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        p = lj.probe(ix, lj.to_device_keys(w.S[a:b])).cpu().numpy().view(np.uint32).copy()
+        p[:, 0] += a
+        parts.append(p)
+    assert np.array_equal(np.concatenate(parts), whole)
+
+
+def test_async_matches_sync_and_checks_workspace():
+    import torch
+    w = workloads.c1_uniform(scale=0.2)
+    want = oracle.sort_merge_join(w.R, w.S)
+    ix = lj.lj_build_rmi(w.R, w.leaves)
+    s = lj.to_device_keys(w.S)
+    nbytes = lj.lj_probe_workspace_bytes(len(w.S))
+    ws = torch.empty(nbytes // 8 + 1, dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    out = torch.empty((len(want) + 5, 2), dtype=torch.int32, device="cuda")
+    for _ in range(3):  # the workspace is reused across calls
+        lj.lj_probe_join_async(ix, s, out, cnt, ws)
+        torch.cuda.synchronize()
+        assert int(cnt.item()) == len(want)
+        assert np.array_equal(out[: len(want)].cpu().numpy().view(np.uint32), want)
+    small = torch.empty(4, dtype=torch.int64, device="cuda")
+    with pytest.raises(lj.LJError) as e:
+        lj.lj_probe_join_async(ix, s, out, cnt, small)
+    assert e.value.status == lj.LJ_ERR_WORKSPACE
+
+
+def test_device_windows_equal_host_windows():
+    import torch
+    for w in (workloads.c1_uniform(scale=0.1), workloads.c2_lognormal_zipf(scale=0.002)):
+        for flags in FLAGS:
+            ix = lj.lj_build_rmi(w.R, w.leaves, flags)
+            keys = np.concatenate([w.R, w.S])
+            leaf_h, lo_h, hi_h = lj.lj_predict_windows_host(ix, keys)
+            kd = lj.to_device_keys(keys)
+            leaf = torch.empty(len(keys), dtype=torch.int32, device="cuda")
+            lo = torch.empty(len(keys), dtype=torch.int64, device="cuda")
+            hi = torch.empty(len(keys), dtype=torch.int64, device="cuda")
+            lj.lj_predict_windows(ix, kd, leaf, lo, hi)
+            torch.cuda.synchronize()
+            assert np.array_equal(leaf.cpu().numpy().view(np.uint32), leaf_h)
+            assert np.array_equal(lo.cpu().numpy(), lo_h)
+            assert np.array_equal(hi.cpu().numpy(), hi_h)

@@ -1,0 +1,151 @@
+"""Host-side tests of liblj.so (no GPU): exports, argument checks and the
+model fit with its error bounds (Section II-D: the RMI keeps min and max
+error bounds per leaf so that a local search around the prediction finds the
+key)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from paper_2111_08824_amd import lj
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+U64MAX = 2**64 - 1
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "lj.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lj_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = lj.lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(lj.EXPORTED)
+
+
+def test_strerror():
+    assert lj.strerror(lj.LJ_OK) == "ok"
+    assert "capacity" in lj.strerror(lj.LJ_ERR_CAPACITY)
+
+
+def _build_status(R, n=None, leaves=4, flags=lj.LJ_LEAF_FP32):
+    R = np.ascontiguousarray(R, dtype=np.uint64)
+    h = ctypes.c_void_p()
+    st = lj.lib().lj_build_rmi_host_only(R.ctypes.data if len(R) else None,
+                                         len(R) if n is None else n, leaves, flags,
+                                         ctypes.byref(h))
+    if h.value:
+        lj.lib().lj_free_index(h.value)
+    return st
+
+
+def test_argument_errors():
+    R = np.array([1, 2, 3], dtype=np.uint64)
+    assert _build_status(R) == lj.LJ_OK
+    assert _build_status(np.array([3, 2], dtype=np.uint64)) == lj.LJ_ERR_UNSORTED
+    assert _build_status(R, leaves=0) == lj.LJ_ERR_ARG
+    assert _build_status(R, flags=0) == lj.LJ_ERR_ARG
+    assert _build_status(R, flags=3) == lj.LJ_ERR_ARG
+    assert _build_status(R, leaves=2**26 + 1) == lj.LJ_ERR_TOO_LARGE
+    assert _build_status(R, n=2**31) == lj.LJ_ERR_TOO_LARGE  # checked before reading R
+    h = ctypes.c_void_p()
+    assert lj.lib().lj_build_rmi_host_only(None, 5, 4, 1, ctypes.byref(h)) == lj.LJ_ERR_ARG
+
+
+def test_probe_of_host_only_index_is_rejected():
+    ix = lj.lj_build_rmi_host_only(np.arange(10, dtype=np.uint64), 2)
+    cnt = ctypes.c_uint64()
+    st = lj.lib().lj_probe_join(ix.handle, None, 0, None, 0, ctypes.byref(cnt), None)
+    assert st == lj.LJ_ERR_ARG
+
+
+def windows_hold(R, leaves, flags):
+    ix = lj.lj_build_rmi_host_only(R, leaves, flags)
+    _, lo, hi = lj.lj_predict_windows_host(ix, R)
+    i = np.arange(len(R))
+    return ix, lo, hi, bool(np.all((lo <= i) & (i <= hi)))
+
+
+@pytest.mark.parametrize("flags", [lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP64])
+@pytest.mark.parametrize("make", [
+    lambda: workloads.c1_uniform().R,
+    lambda: workloads.c2_lognormal_zipf(scale=0.005).R,
+    lambda: workloads.c3_dup_runs(scale=0.005).R,
+    lambda: workloads.gen.seq_holes(300_000, 9),
+])
+def test_every_key_of_r_lies_in_its_window(make, flags):
+    R = make()
+    for leaves in (1, 7, workloads.default_leaves(len(R)), 4 * len(R) + 3):
+        _, _, _, ok = windows_hold(R, leaves, flags)
+        assert ok, leaves
+
+
+def test_windows_contain_all_matches_of_every_probe():
+    # Host model + window + oracle equal_range: every copy of a probed key of
+    # R sits inside that key's window, so a search restricted to the window
+    # finds exactly the oracle's run.
+    w = workloads.c3_dup_runs(scale=0.002)
+    ix = lj.lj_build_rmi_host_only(w.R, w.leaves, lj.LJ_LEAF_FP32)
+    _, lo, hi = lj.lj_predict_windows_host(ix, w.S)
+    first, count = oracle.equal_range(w.R, w.S)
+    hit = count > 0
+    assert hit.sum() > 0
+    assert np.all(lo[hit] <= first[hit].astype(np.int64))
+    assert np.all((first[hit] + count[hit] - 1).astype(np.int64) <= hi[hit])
+
+
+def test_arithmetic_keys_have_exact_fp64_models():
+    # x_i = c + d*i is exactly linear, so each leaf's FP64 least-squares line
+    # reproduces every offset and all error bounds are zero: the window of
+    # each key is its own position.
+    R = (np.uint64(1000) + np.uint64(37) * np.arange(50_000, dtype=np.uint64))
+    ix, lo, hi, ok = windows_hold(R, 64, lj.LJ_LEAF_FP64)
+    assert ok
+    i = np.arange(len(R))
+    assert np.array_equal(lo, i) and np.array_equal(hi, i)
+    assert ix.stats.mean_window == 1.0
+
+
+def test_single_distinct_key_leaf_spans_its_run():
+    R = np.array([5] * 100 + [9] * 3, dtype=np.uint64)
+    ix, lo, hi, ok = windows_hold(R, 1, lj.LJ_LEAF_FP32)
+    assert ok
+    st = ix.stats
+    assert st.max_mult == 100
+
+
+def test_empty_relation_and_extreme_keys():
+    ix = lj.lj_build_rmi_host_only(np.empty(0, dtype=np.uint64), 8)
+    leaf, lo, hi = lj.lj_predict_windows_host(ix, np.array([0, 5, U64MAX], dtype=np.uint64))
+    assert np.all(lo > hi)  # empty windows
+    R = np.array([0, 1, 2**63, U64MAX - 1, U64MAX], dtype=np.uint64)
+    for flags in (lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP64):
+        _, _, _, ok = windows_hold(R, 3, flags)
+        assert ok
+
+
+def test_fp32_and_fp64_bounds_are_close():
+    # The FP32 leaf model is the FP64 fit rounded to f32 with bounds
+    # recomputed under f32 arithmetic; on the lognormal workload its windows
+    # are not much wider than the FP64 ones.
+    R = workloads.c2_lognormal_zipf(scale=0.005).R
+    s32 = lj.lj_build_rmi_host_only(R, 4096, lj.LJ_LEAF_FP32).stats
+    s64 = lj.lj_build_rmi_host_only(R, 4096, lj.LJ_LEAF_FP64).stats
+    assert s32.mean_window <= 1.05 * s64.mean_window + 2
+
+
+def test_root_is_monotone_and_covers_leaves():
+    R = workloads.c1_uniform().R
+    ix = lj.lj_build_rmi_host_only(R, 4096)
+    leaf, _, _ = lj.lj_predict_windows_host(ix, R)
+    assert np.all(np.diff(leaf.astype(np.int64)) >= 0)
+    assert ix.stats.nonempty_leaves == 4096
