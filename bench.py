@@ -109,7 +109,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lognormal-zipf-200M")
     ap.add_argument("--leaf", choices=["fp32", "fp64"], default="fp32")
-    ap.add_argument("--cpu-sample", type=int, default=40_000_000,
+    ap.add_argument("--cpu-sample", type=int, default=120_000_000,
                     help="outer keys in the timed oracle sample (0 = skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the steps, run a plain device copy of this many MiB "
@@ -147,6 +147,9 @@ def main():
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
+    for a, b in ev:  # materialise the HIP events; the library re-records them
+        a.record(stream)
+        b.record(stream)
     lat = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()

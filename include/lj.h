@@ -99,8 +99,8 @@ void lj_free_index(lj_index* index);
  *
  *   s_keys_dev     m outer keys in device memory (any alignment of 8).
  *   m              number of outer keys, 0 <= m < 2^32.
- *   out_pairs_dev  room for out_capacity pairs, or NULL when out_capacity
- *                  is 0 (count-only probe).
+ *   out_pairs_dev  room for out_capacity pairs, or NULL with out_capacity
+ *                  0 for a count-only probe (which returns LJ_OK).
  *   out_count_host receives the total number of matching pairs.
  *
  * Capacity protocol (like snprintf): the pairs whose rank in the output
@@ -169,23 +169,26 @@ int lj_self_check(const lj_index* index, uint64_t* out_violations_host,
                   hipStream_t stream);
 
 /*
- * Window diagnostics: for each of m keys (device memory), the absolute
- * search window [lo, hi] the probe searches (lo > hi = empty window) and
- * the leaf chosen by the root.  Used by tests and for the model-quality
- * statistics; not part of the join.  Asynchronous on `stream`.
+ * Window diagnostics: for each of m keys (device memory), the leaf chosen by
+ * the root, the predicted absolute position (-1 for an empty leaf) and the
+ * absolute search window [lo, hi] the probe searches (lo > hi = empty
+ * window).  Used by tests and for model-quality statistics; not part of the
+ * join.  Any output pointer may be NULL.  Asynchronous on `stream`.
  */
 int lj_predict_windows(const lj_index* index, const uint64_t* keys_dev,
-                       uint64_t m, uint32_t* leaf_dev, int64_t* win_lo_dev,
-                       int64_t* win_hi_dev, hipStream_t stream);
+                       uint64_t m, uint32_t* leaf_dev, int64_t* pred_dev,
+                       int64_t* win_lo_dev, int64_t* win_hi_dev,
+                       hipStream_t stream);
 
 /*
- * Host-side model evaluation for tests without a GPU: the same leaf choice
- * and window as lj_predict_windows, computed on the CPU from an index's
- * host copy of the model.
+ * Host-side model evaluation for tests without a GPU: the same leaf choice,
+ * prediction and window as lj_predict_windows, computed on the CPU from an
+ * index's host copy of the model.
  */
 int lj_predict_windows_host(const lj_index* index, const uint64_t* keys_host,
                             uint64_t m, uint32_t* leaf_host,
-                            int64_t* win_lo_host, int64_t* win_hi_host);
+                            int64_t* pred_host, int64_t* win_lo_host,
+                            int64_t* win_hi_host);
 
 /*
  * Build only the host-side model (no device allocation) so that the fit and

@@ -207,7 +207,8 @@ int lj_probe_join(const lj_index* idx, const uint64_t* s, uint64_t m, lj_pair* o
     const uint64_t total = *t_host_count;
     if (total == ~0ull) return LJ_ERR_DEVICE;
     *count_host = total;
-    return total > cap ? LJ_ERR_CAPACITY : LJ_OK;
+    // A count-only probe (no output buffer) is not a capacity error.
+    return (out && total > cap) ? LJ_ERR_CAPACITY : LJ_OK;
 }
 
 int lj_index_get_stats(const lj_index* idx, lj_index_stats* o) {
@@ -242,22 +243,22 @@ int lj_self_check(const lj_index* idx, uint64_t* viol_host, hipStream_t stream) 
 }
 
 int lj_predict_windows(const lj_index* idx, const uint64_t* keys, uint64_t m, uint32_t* leaf,
-                       int64_t* wlo, int64_t* whi, hipStream_t stream) {
+                       int64_t* pred, int64_t* wlo, int64_t* whi, hipStream_t stream) {
     if (!idx || idx->host_only || (m && !keys)) return LJ_ERR_ARG;
     int st = check_device(idx);
     if (st != LJ_OK) return st;
-    return lj::launch_predict_windows(idx, keys, m, leaf, wlo, whi, stream) == hipSuccess
+    return lj::launch_predict_windows(idx, keys, m, leaf, pred, wlo, whi, stream) == hipSuccess
                ? LJ_OK
                : LJ_ERR_DEVICE;
 }
 
 int lj_predict_windows_host(const lj_index* idx, const uint64_t* keys, uint64_t m,
-                            uint32_t* leaf, int64_t* wlo, int64_t* whi) {
+                            uint32_t* leaf, int64_t* pred, int64_t* wlo, int64_t* whi) {
     if (!idx || (m && !keys)) return LJ_ERR_ARG;
     for (uint64_t i = 0; i < m; ++i) {
         uint64_t x = keys[i];
         uint32_t l = lj::route(idx->root, x);
-        int64_t lo = 1, hi = 0;
+        int64_t lo = 1, hi = 0, pr = -1;
         uint32_t cnt = 0, pos0 = 0;
         int32_t elo = 0, ehi = 0, rel = 0;
         if (idx->flags == LJ_LEAF_FP32) {
@@ -276,6 +277,7 @@ int lj_predict_windows_host(const lj_index* idx, const uint64_t* keys, uint64_t 
             ehi = lf.hi;
         }
         if (cnt) {
+            pr = (int64_t)pos0 + rel;
             int64_t a = (int64_t)rel + elo, b = (int64_t)rel + ehi;
             if (a < 0) a = 0;
             if (b > (int64_t)cnt - 1) b = (int64_t)cnt - 1;
@@ -285,6 +287,7 @@ int lj_predict_windows_host(const lj_index* idx, const uint64_t* keys, uint64_t 
             }
         }
         if (leaf) leaf[i] = l;
+        if (pred) pred[i] = pr;
         if (wlo) wlo[i] = lo;
         if (whi) whi[i] = hi;
     }

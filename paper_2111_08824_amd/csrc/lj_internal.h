@@ -66,7 +66,7 @@ hipError_t launch_set_u64(uint64_t* p, uint64_t v, hipStream_t stream);
 hipError_t launch_self_check(const lj_index* idx, uint64_t* violations_dev,
                              hipStream_t stream);
 hipError_t launch_predict_windows(const lj_index* idx, const uint64_t* keys,
-                                  uint64_t m, uint32_t* leaf, int64_t* wlo,
-                                  int64_t* whi, hipStream_t stream);
+                                  uint64_t m, uint32_t* leaf, int64_t* pred,
+                                  int64_t* wlo, int64_t* whi, hipStream_t stream);
 
 }  // namespace lj

@@ -400,16 +400,17 @@ __global__ void self_check_kernel(const uint64_t* R, uint64_t n, const Leaf* lea
 
 template <class Leaf>
 __global__ void predict_windows_kernel(const uint64_t* keys, uint64_t m, const Leaf* leaves,
-                                       RootModel root, uint32_t* leaf_out, int64_t* wlo,
-                                       int64_t* whi) {
+                                       RootModel root, uint32_t* leaf_out, int64_t* pred,
+                                       int64_t* wlo, int64_t* whi) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
          i += (uint64_t)gridDim.x * blockDim.x) {
         uint64_t x = keys[i];
         uint32_t l = route(root, x);
         const Leaf lf = leaves[l];
-        int64_t lo = 1, hi = 0;
+        int64_t lo = 1, hi = 0, pr = -1;
         if (lf.cnt != 0) {
             int64_t rel = predict_rel(lf, x);
+            pr = (int64_t)lf.pos0 + rel;
             int64_t a = rel + lf.lo, b = rel + lf.hi;
             if (a < 0) a = 0;
             if (b > (int64_t)lf.cnt - 1) b = (int64_t)lf.cnt - 1;
@@ -419,6 +420,7 @@ __global__ void predict_windows_kernel(const uint64_t* keys, uint64_t m, const L
             }
         }
         if (leaf_out) leaf_out[i] = l;
+        if (pred) pred[i] = pr;
         if (wlo) wlo[i] = lo;
         if (whi) whi[i] = hi;
     }
@@ -497,16 +499,18 @@ hipError_t launch_self_check(const lj_index* idx, uint64_t* viol, hipStream_t st
 }
 
 hipError_t launch_predict_windows(const lj_index* idx, const uint64_t* keys, uint64_t m,
-                                  uint32_t* leaf, int64_t* wlo, int64_t* whi,
+                                  uint32_t* leaf, int64_t* pred, int64_t* wlo, int64_t* whi,
                                   hipStream_t stream) {
     if (m == 0) return hipSuccess;
     unsigned g = grid_for(m, 256);
     if (idx->flags == LJ_LEAF_FP32)
         hipLaunchKernelGGL(predict_windows_kernel<LeafF32>, dim3(g), dim3(256), 0, stream,
-                           keys, m, (const LeafF32*)idx->leaf_dev, idx->root, leaf, wlo, whi);
+                           keys, m, (const LeafF32*)idx->leaf_dev, idx->root, leaf, pred, wlo,
+                           whi);
     else
         hipLaunchKernelGGL(predict_windows_kernel<LeafF64>, dim3(g), dim3(256), 0, stream,
-                           keys, m, (const LeafF64*)idx->leaf_dev, idx->root, leaf, wlo, whi);
+                           keys, m, (const LeafF64*)idx->leaf_dev, idx->root, leaf, pred, wlo,
+                           whi);
     return hipGetLastError();
 }
 

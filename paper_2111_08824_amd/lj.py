@@ -83,8 +83,8 @@ def lib() -> ctypes.CDLL:
         L.lj_probe_join_async.argtypes = [vp, vp, u64, vp, u64, vp, vp, u64, vp]
         L.lj_index_get_stats.argtypes = [vp, ctypes.POINTER(lj_index_stats)]
         L.lj_self_check.argtypes = [vp, ctypes.POINTER(u64), vp]
-        L.lj_predict_windows.argtypes = [vp, vp, u64, vp, vp, vp, vp]
-        L.lj_predict_windows_host.argtypes = [vp, vp, u64, vp, vp, vp]
+        L.lj_predict_windows.argtypes = [vp, vp, u64, vp, vp, vp, vp, vp]
+        L.lj_predict_windows_host.argtypes = [vp, vp, u64, vp, vp, vp, vp]
         L.lj_probe_set_timing_events.argtypes = [vp, vp]
         L.lj_strerror.argtypes = [i32]
         L.lj_strerror.restype = ctypes.c_char_p
@@ -209,22 +209,26 @@ def lj_self_check(index: Index, stream=None) -> int:
     return v.value
 
 
-def lj_predict_windows(index: Index, keys_dev, leaf_dev, lo_dev, hi_dev, stream=None) -> None:
+def lj_predict_windows(index: Index, keys_dev, leaf_dev, pred_dev, lo_dev, hi_dev,
+                       stream=None) -> None:
     _check(lib().lj_predict_windows(index.handle, _dev_ptr(keys_dev), keys_dev.numel(),
-                                    _dev_ptr(leaf_dev), _dev_ptr(lo_dev), _dev_ptr(hi_dev),
-                                    _stream_ptr(stream)), "lj_predict_windows")
+                                    _dev_ptr(leaf_dev), _dev_ptr(pred_dev), _dev_ptr(lo_dev),
+                                    _dev_ptr(hi_dev), _stream_ptr(stream)),
+           "lj_predict_windows")
 
 
 def lj_predict_windows_host(index: Index, keys):
+    """(leaf, pred, lo, hi) arrays for host keys."""
     keys = _host_u64(keys)
     m = len(keys)
     leaf = np.empty(m, dtype=np.uint32)
+    pred = np.empty(m, dtype=np.int64)
     lo = np.empty(m, dtype=np.int64)
     hi = np.empty(m, dtype=np.int64)
     _check(lib().lj_predict_windows_host(index.handle, keys.ctypes.data if m else None, m,
-                                         leaf.ctypes.data, lo.ctypes.data, hi.ctypes.data),
-           "lj_predict_windows_host")
-    return leaf, lo, hi
+                                         leaf.ctypes.data, pred.ctypes.data, lo.ctypes.data,
+                                         hi.ctypes.data), "lj_predict_windows_host")
+    return leaf, pred, lo, hi
 
 
 def lj_probe_set_timing_events(start, stop) -> None:

@@ -165,13 +165,15 @@ def test_device_windows_equal_host_windows():
         for flags in FLAGS:
             ix = lj.lj_build_rmi(w.R, w.leaves, flags)
             keys = np.concatenate([w.R, w.S])
-            leaf_h, lo_h, hi_h = lj.lj_predict_windows_host(ix, keys)
+            leaf_h, pred_h, lo_h, hi_h = lj.lj_predict_windows_host(ix, keys)
             kd = lj.to_device_keys(keys)
             leaf = torch.empty(len(keys), dtype=torch.int32, device="cuda")
+            pred = torch.empty(len(keys), dtype=torch.int64, device="cuda")
             lo = torch.empty(len(keys), dtype=torch.int64, device="cuda")
             hi = torch.empty(len(keys), dtype=torch.int64, device="cuda")
-            lj.lj_predict_windows(ix, kd, leaf, lo, hi)
+            lj.lj_predict_windows(ix, kd, leaf, pred, lo, hi)
             torch.cuda.synchronize()
             assert np.array_equal(leaf.cpu().numpy().view(np.uint32), leaf_h)
+            assert np.array_equal(pred.cpu().numpy(), pred_h)
             assert np.array_equal(lo.cpu().numpy(), lo_h)
             assert np.array_equal(hi.cpu().numpy(), hi_h)

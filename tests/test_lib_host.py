@@ -70,7 +70,7 @@ def test_probe_of_host_only_index_is_rejected():
 
 def windows_hold(R, leaves, flags):
     ix = lj.lj_build_rmi_host_only(R, leaves, flags)
-    _, lo, hi = lj.lj_predict_windows_host(ix, R)
+    _, _, lo, hi = lj.lj_predict_windows_host(ix, R)
     i = np.arange(len(R))
     return ix, lo, hi, bool(np.all((lo <= i) & (i <= hi)))
 
@@ -95,7 +95,7 @@ def test_windows_contain_all_matches_of_every_probe():
     # finds exactly the oracle's run.
     w = workloads.c3_dup_runs(scale=0.002)
     ix = lj.lj_build_rmi_host_only(w.R, w.leaves, lj.LJ_LEAF_FP32)
-    _, lo, hi = lj.lj_predict_windows_host(ix, w.S)
+    _, _, lo, hi = lj.lj_predict_windows_host(ix, w.S)
     first, count = oracle.equal_range(w.R, w.S)
     hit = count > 0
     assert hit.sum() > 0
@@ -125,7 +125,8 @@ def test_single_distinct_key_leaf_spans_its_run():
 
 def test_empty_relation_and_extreme_keys():
     ix = lj.lj_build_rmi_host_only(np.empty(0, dtype=np.uint64), 8)
-    leaf, lo, hi = lj.lj_predict_windows_host(ix, np.array([0, 5, U64MAX], dtype=np.uint64))
+    leaf, pred, lo, hi = lj.lj_predict_windows_host(ix, np.array([0, 5, U64MAX], dtype=np.uint64))
+    assert np.all(pred == -1)
     assert np.all(lo > hi)  # empty windows
     R = np.array([0, 1, 2**63, U64MAX - 1, U64MAX], dtype=np.uint64)
     for flags in (lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP64):
@@ -146,6 +147,6 @@ def test_fp32_and_fp64_bounds_are_close():
 def test_root_is_monotone_and_covers_leaves():
     R = workloads.c1_uniform().R
     ix = lj.lj_build_rmi_host_only(R, 4096)
-    leaf, _, _ = lj.lj_predict_windows_host(ix, R)
+    leaf, _, _, _ = lj.lj_predict_windows_host(ix, R)
     assert np.all(np.diff(leaf.astype(np.int64)) >= 0)
     assert ix.stats.nonempty_leaves == 4096
