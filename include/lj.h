@@ -208,6 +208,19 @@ int lj_build_rmi_host_only(const uint64_t* r_keys_host, uint64_t n,
  */
 int lj_probe_set_timing_events(hipEvent_t start, hipEvent_t stop);
 
+/*
+ * Random-access ceiling for the roofline: reads `reads` 8-byte words, each
+ * from a pseudo-random `granule`-byte aligned block of the device buffer
+ * `buf_dev` (`bytes` long), with every lane keeping 8 independent loads in
+ * flight; a checksum goes to `sink_dev` (one u64) so no load is elided.
+ * Asynchronous on `stream`; time it with events.  `granule` is a power of
+ * two in [8, 4096] and `bytes` at least `granule`.  Errors: LJ_ERR_ARG,
+ * LJ_ERR_DEVICE.
+ */
+int lj_bench_random_gather(const void* buf_dev, uint64_t bytes,
+                           uint32_t granule, uint64_t reads, uint64_t seed,
+                           uint64_t* sink_dev, hipStream_t stream);
+
 /* Static description of a status code. */
 const char* lj_strerror(int status);
 

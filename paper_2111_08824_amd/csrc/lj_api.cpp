@@ -294,6 +294,17 @@ int lj_predict_windows_host(const lj_index* idx, const uint64_t* keys, uint64_t 
     return LJ_OK;
 }
 
+int lj_bench_random_gather(const void* buf, uint64_t bytes, uint32_t granule, uint64_t reads,
+                           uint64_t seed, uint64_t* sink, hipStream_t stream) {
+    if (!buf || !sink || granule < 8 || granule > 4096 || (granule & (granule - 1)) ||
+        bytes < granule)
+        return LJ_ERR_ARG;
+    return lj::launch_random_gather(buf, bytes, granule, reads, seed, sink, stream) ==
+                   hipSuccess
+               ? LJ_OK
+               : LJ_ERR_DEVICE;
+}
+
 const char* lj_strerror(int s) {
     switch (s) {
         case LJ_OK: return "ok";

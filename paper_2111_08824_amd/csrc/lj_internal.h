@@ -5,7 +5,7 @@
 
 #include <vector>
 
-#include "../../include/lj.h"
+#include "lj.h"
 #include "rmi_eval.h"
 
 struct lj_index {
@@ -39,10 +39,14 @@ namespace lj {
 int fit_rmi(const uint64_t* r, uint64_t n, uint32_t leaves, uint32_t flags,
             lj_index* idx);
 
-// Tile geometry of the fused probe kernel.
+// Tile geometry of the fused probe kernel: kBlock threads, each holding
+// kItems outer keys (kItemsUnique when R has no duplicate keys, kItemsDup
+// otherwise, where the run scan and the LDS offsets need more room).
 constexpr int kBlock = 256;
-constexpr int kItems = 4;
-constexpr int kTile = kBlock * kItems;
+constexpr int kItemsUnique = 24;
+constexpr int kItemsDup = 16;
+constexpr int kSetupChunk = 4;
+constexpr int kMinTile = kBlock * 8;  // smallest tile any launch uses
 
 // Workspace: a 256-byte header followed by one status word per tile.
 struct WsHeader {
@@ -54,8 +58,9 @@ struct WsHeader {
 };
 constexpr uint64_t kWsHeaderBytes = 256;
 
-inline uint64_t num_tiles(uint64_t m) { return (m + kTile - 1) / kTile; }
-inline uint64_t ws_bytes(uint64_t m) { return kWsHeaderBytes + num_tiles(m) * 8; }
+inline uint64_t num_tiles(uint64_t m, uint64_t tile) { return (m + tile - 1) / tile; }
+// Sized for the smallest tile, so one workspace fits every launch shape.
+inline uint64_t ws_bytes(uint64_t m) { return kWsHeaderBytes + num_tiles(m, kMinTile) * 8; }
 
 // Kernel launchers (lj_kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m,
@@ -68,5 +73,9 @@ hipError_t launch_self_check(const lj_index* idx, uint64_t* violations_dev,
 hipError_t launch_predict_windows(const lj_index* idx, const uint64_t* keys,
                                   uint64_t m, uint32_t* leaf, int64_t* pred,
                                   int64_t* wlo, int64_t* whi, hipStream_t stream);
+
+hipError_t launch_random_gather(const void* buf, uint64_t bytes, uint32_t granule,
+                                uint64_t reads, uint64_t seed, uint64_t* sink,
+                                hipStream_t stream);
 
 }  // namespace lj

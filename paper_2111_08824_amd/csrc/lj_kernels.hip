@@ -164,13 +164,13 @@ __device__ void finish_tile(const ProbeParams& p) {
     }
 }
 
-template <class Leaf, bool kUnique>
+template <class Leaf, bool kUnique, int kItems>
 __global__ __launch_bounds__(kBlock) void probe_join_kernel(ProbeParams p) {
     __shared__ uint32_t s_tile;
     __shared__ uint64_t s_excl;
     __shared__ uint64_t s_wsum[kItems * (kBlock / 64)];
-    __shared__ uint64_t s_off[kUnique ? 1 : kTile + 1];
-    __shared__ uint32_t s_j0[kUnique ? 1 : kTile];
+    __shared__ uint64_t s_off[kUnique ? 1 : (kBlock * kItems) + 1];
+    __shared__ uint32_t s_j0[kUnique ? 1 : (kBlock * kItems)];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -179,43 +179,51 @@ __global__ __launch_bounds__(kBlock) void probe_join_kernel(ProbeParams p) {
     if (tid == 0) s_tile = atomicAdd(&p.hdr->tile_counter, 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
-    const uint64_t tbase = (uint64_t)tile * kTile;
+    const uint64_t tbase = (uint64_t)tile * (kBlock * kItems);
     const Leaf* leaves = (const Leaf*)p.leaves;
     const uint64_t* __restrict__ R = p.r;
 
     uint64_t x[kItems];
-    uint32_t first[kItems], len[kItems], end[kItems];
-    uint64_t gev[kItems];
-    bool valid[kItems];
+    uint32_t first[kItems], len[kItems];
+    uint32_t end[kUnique ? 1 : kItems];
+    uint32_t eqmask = 0;  // bit k: the last R[mid] >= x[k] read equals x[k]
+    static_assert(kItems <= 32, "eqmask holds one bit per key");
 
-    // 1: keys.  Loads are unconditional (clamped index) so that the four
+    // 1: keys.  Loads are unconditional (clamped index) so that all the
     // loads of a lane are in flight together.
+    uint32_t validmask = 0;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         uint64_t s = tbase + (uint64_t)k * kBlock + tid;
-        valid[k] = s < p.m;
-        x[k] = p.s[valid[k] ? s : p.m - 1];
+        validmask |= (s < p.m ? 1u : 0u) << k;
+        x[k] = p.s[s < p.m ? s : p.m - 1];
     }
-    // 2: root model, leaf record, leaf model, window.
-    Leaf lf[kItems];
+    // 2: root model, leaf record, leaf model, window; kSetupChunk records
+    // in flight at a time to bound register use.
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) lf[k] = load_leaf(leaves + route(p.root, x[k]));
+    for (int k0 = 0; k0 < kItems; k0 += kSetupChunk) {
+        Leaf lf[kSetupChunk];
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        int64_t rel = predict_rel(lf[k], x[k]);
-        int64_t wlo = rel + lf[k].lo, whi = rel + lf[k].hi;
-        if (wlo < 0) wlo = 0;
-        if (whi > (int64_t)lf[k].cnt - 1) whi = (int64_t)lf[k].cnt - 1;
-        const bool live = valid[k] && lf[k].cnt != 0 && wlo <= whi;
-        first[k] = live ? lf[k].pos0 + (uint32_t)wlo : 0;
-        len[k] = live ? (uint32_t)(whi - wlo + 1) : 0;
-        end[k] = live ? lf[k].pos0 + (uint32_t)whi + 1 : 0;
-        gev[k] = 0;
+        for (int j = 0; j < kSetupChunk; ++j) lf[j] = load_leaf(leaves + route(p.root, x[k0 + j]));
+#pragma unroll
+        for (int j = 0; j < kSetupChunk; ++j) {
+            const int k = k0 + j;
+            int64_t rel = predict_rel(lf[j], x[k]);
+            int64_t wlo = rel + lf[j].lo, whi = rel + lf[j].hi;
+            if (wlo < 0) wlo = 0;
+            if (whi > (int64_t)lf[j].cnt - 1) whi = (int64_t)lf[j].cnt - 1;
+            const bool live = ((validmask >> k) & 1u) && lf[j].cnt != 0 && wlo <= whi;
+            first[k] = live ? lf[j].pos0 + (uint32_t)wlo : 0;
+            len[k] = live ? (uint32_t)(whi - wlo + 1) : 0;
+            if (!kUnique) end[k] = live ? lf[j].pos0 + (uint32_t)whi + 1 : 0;
+        }
     }
 
     // 3: lockstep lower_bound over the windows.  Finished keys re-read R[0]
     // (a cached line) so that the loop body has no branches and the loads of
-    // the kItems keys issue back to back.
+    // all keys of the lane issue back to back.  When the loop ends, first[k]
+    // is the window end or the position of the last element read with
+    // R[mid] >= x[k], so bit k of eqmask tells whether x[k] was found.
     for (;;) {
         uint32_t anylen = 0;
 #pragma unroll
@@ -230,48 +238,53 @@ __global__ __launch_bounds__(kBlock) void probe_join_kernel(ProbeParams p) {
             const bool act = len[k] != 0;
             const bool lt = v[k] < x[k];
             first[k] = (act && lt) ? first[k] + half + 1 : first[k];
-            gev[k] = (act && !lt) ? v[k] : gev[k];
+            if (act && !lt) eqmask = (eqmask & ~(1u << k)) | ((v[k] == x[k] ? 1u : 0u) << k);
             len[k] = act ? (lt ? len[k] - half - 1 : half) : 0;
         }
     }
 
-    // 4: run lengths.  first[k] < end[k] means R[first[k]] == gev[k] >= x[k].
+    // 4: run lengths.
     uint32_t c[kItems];
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) c[k] = (first[k] < end[k] && gev[k] == x[k]) ? 1u : 0u;
+    for (int k = 0; k < kItems; ++k) c[k] = (eqmask >> k) & 1u;
     if (!kUnique) {
-        // Forward scan of equal keys, four at a time, bounded by the window.
-        uint32_t cur[kItems];
-        bool act[kItems];
+        // Forward scan of equal keys, four positions at a time, bounded by
+        // the window; kSetupChunk keys per pass to bound register use.  The
+        // lines read here are the ones the search just touched.
 #pragma unroll
-        for (int k = 0; k < kItems; ++k) {
-            cur[k] = first[k] + 1;
-            act[k] = c[k] && cur[k] < end[k];
-        }
-        for (;;) {
-            bool any = false;
+        for (int k0 = 0; k0 < kItems; k0 += kSetupChunk) {
+            uint32_t cur[kSetupChunk];
+            bool act[kSetupChunk];
 #pragma unroll
-            for (int k = 0; k < kItems; ++k) any |= act[k];
-            if (!any) break;
-            uint64_t v[kItems][4];
+            for (int j = 0; j < kSetupChunk; ++j) {
+                cur[j] = first[k0 + j] + 1;
+                act[j] = c[k0 + j] && cur[j] < end[k0 + j];
+            }
+            for (;;) {
+                bool any = false;
 #pragma unroll
-            for (int k = 0; k < kItems; ++k)
+                for (int j = 0; j < kSetupChunk; ++j) any |= act[j];
+                if (!any) break;
+                uint64_t v[kSetupChunk][4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const bool in = act[k] && cur[k] + u < end[k];
-                    v[k][u] = R[in ? cur[k] + u : 0];
-                    if (!in) v[k][u] = ~x[k];
+                for (int j = 0; j < kSetupChunk; ++j)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const bool in = act[j] && cur[j] + u < end[k0 + j];
+                        v[j][u] = R[in ? cur[j] + u : 0];
+                        if (!in) v[j][u] = ~x[k0 + j];
+                    }
+#pragma unroll
+                for (int j = 0; j < kSetupChunk; ++j) {
+                    bool run = act[j];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        run = run && v[j][u] == x[k0 + j];
+                        c[k0 + j] += run ? 1u : 0u;
+                    }
+                    cur[j] += 4;
+                    act[j] = run && cur[j] < end[k0 + j];
                 }
-#pragma unroll
-            for (int k = 0; k < kItems; ++k) {
-                bool run = act[k];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    run = run && v[k][u] == x[k];
-                    c[k] += run ? 1u : 0u;
-                }
-                cur[k] += 4;
-                act[k] = run && cur[k] < end[k];
             }
         }
     }
@@ -343,7 +356,7 @@ __global__ __launch_bounds__(kBlock) void probe_join_kernel(ProbeParams p) {
         const uint64_t texcl = wpre + incl - tsum;
 #pragma unroll
         for (int i = 0; i < kItems; ++i) s_off[tid * kItems + i] = texcl + loc[i];
-        if (tid == 0) s_off[kTile] = total;
+        if (tid == 0) s_off[(kBlock * kItems)] = total;
         // 6: look-back.
         if (wave == 0) {
             uint64_t e = look_back(p.status, tile, total, &p.hdr->err, lane);
@@ -356,7 +369,7 @@ __global__ __launch_bounds__(kBlock) void probe_join_kernel(ProbeParams p) {
             uint64_t limit = p.cap - excl < total ? p.cap - excl : total;
             for (uint64_t o = tid; o < limit; o += kBlock) {
                 // last q with s_off[q] <= o
-                int lo = 0, hi = kTile;  // s_off[kTile] = total > o
+                int lo = 0, hi = (kBlock * kItems);  // s_off[(kBlock * kItems)] = total > o
                 while (hi - lo > 1) {
                     int mid = (lo + hi) >> 1;
                     if (s_off[mid] <= o) lo = mid;
@@ -442,8 +455,10 @@ hipError_t launch_set_u64(uint64_t* p, uint64_t v, hipStream_t stream) {
 hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m, lj_pair* out,
                         uint64_t cap, uint64_t* count_dev, void* ws, hipStream_t stream,
                         hipEvent_t ev0, hipEvent_t ev1) {
-    const uint64_t nt = num_tiles(m);
-    const uint64_t words = ws_bytes(m) / 8;
+    const bool uniq = idx->max_mult <= 1;
+    const bool f32 = idx->flags == LJ_LEAF_FP32;
+    const uint64_t nt = num_tiles(m, kBlock * (uniq ? kItemsUnique : kItemsDup));
+    const uint64_t words = (kWsHeaderBytes + nt * 8) / 8;
     hipLaunchKernelGGL(zero_words, dim3(grid_for(words, 256)), dim3(256), 0, stream,
                        (uint64_t*)ws, words);
     hipError_t e = hipGetLastError();
@@ -462,21 +477,24 @@ hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m, lj_p
     p.status = (uint64_t*)((char*)ws + kWsHeaderBytes);
     p.ntiles = (uint32_t)nt;
 
-    const bool uniq = idx->max_mult <= 1;
-    const bool f32 = idx->flags == LJ_LEAF_FP32;
+
     if (ev0) {
         e = hipEventRecord(ev0, stream);
         if (e != hipSuccess) return e;
     }
     dim3 grid((unsigned)nt), block(kBlock);
     if (f32 && uniq)
-        hipLaunchKernelGGL((probe_join_kernel<LeafF32, true>), grid, block, 0, stream, p);
+        hipLaunchKernelGGL((probe_join_kernel<LeafF32, true, kItemsUnique>), grid, block, 0,
+                           stream, p);
     else if (f32)
-        hipLaunchKernelGGL((probe_join_kernel<LeafF32, false>), grid, block, 0, stream, p);
+        hipLaunchKernelGGL((probe_join_kernel<LeafF32, false, kItemsDup>), grid, block, 0,
+                           stream, p);
     else if (uniq)
-        hipLaunchKernelGGL((probe_join_kernel<LeafF64, true>), grid, block, 0, stream, p);
+        hipLaunchKernelGGL((probe_join_kernel<LeafF64, true, kItemsUnique>), grid, block, 0,
+                           stream, p);
     else
-        hipLaunchKernelGGL((probe_join_kernel<LeafF64, false>), grid, block, 0, stream, p);
+        hipLaunchKernelGGL((probe_join_kernel<LeafF64, false, kItemsDup>), grid, block, 0,
+                           stream, p);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev1) e = hipEventRecord(ev1, stream);

@@ -33,7 +33,7 @@ EXPORTED = (
     "lj_build_rmi", "lj_free_index", "lj_probe_join", "lj_probe_workspace_bytes",
     "lj_probe_join_async", "lj_index_get_stats", "lj_self_check", "lj_predict_windows",
     "lj_predict_windows_host", "lj_build_rmi_host_only", "lj_probe_set_timing_events",
-    "lj_strerror",
+    "lj_bench_random_gather", "lj_strerror",
 )
 
 
@@ -86,12 +86,13 @@ def lib() -> ctypes.CDLL:
         L.lj_predict_windows.argtypes = [vp, vp, u64, vp, vp, vp, vp, vp]
         L.lj_predict_windows_host.argtypes = [vp, vp, u64, vp, vp, vp, vp]
         L.lj_probe_set_timing_events.argtypes = [vp, vp]
+        L.lj_bench_random_gather.argtypes = [vp, u64, u32, u64, u64, vp, vp]
         L.lj_strerror.argtypes = [i32]
         L.lj_strerror.restype = ctypes.c_char_p
         for f in ("lj_build_rmi", "lj_build_rmi_host_only", "lj_probe_join",
                   "lj_probe_join_async", "lj_index_get_stats", "lj_self_check",
                   "lj_predict_windows", "lj_predict_windows_host",
-                  "lj_probe_set_timing_events"):
+                  "lj_probe_set_timing_events", "lj_bench_random_gather"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -236,6 +237,14 @@ def lj_probe_set_timing_events(start, stop) -> None:
     _check(lib().lj_probe_set_timing_events(
         start.cuda_event if start is not None else None,
         stop.cuda_event if stop is not None else None), "lj_probe_set_timing_events")
+
+
+def lj_bench_random_gather(buf_dev, granule: int, reads: int, seed: int, sink_dev,
+                           stream=None) -> None:
+    nbytes = buf_dev.numel() * buf_dev.element_size()
+    _check(lib().lj_bench_random_gather(_dev_ptr(buf_dev), nbytes, granule, reads, seed,
+                                        _dev_ptr(sink_dev), _stream_ptr(stream)),
+           "lj_bench_random_gather")
 
 
 # ---------------------------------------------------------------------------
