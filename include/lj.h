@@ -142,6 +142,80 @@ int lj_probe_join_async(const lj_index* index, const uint64_t* s_keys_dev,
                         void* workspace_dev, uint64_t workspace_bytes,
                         hipStream_t stream);
 
+/*
+ * Batched probe of many indexes as one replayable unit.
+ *
+ * Each descriptor is one independent probe with the semantics and capacity
+ * protocol of lj_probe_join_async: the keys of s_keys_dev against `index`,
+ * pairs into out_pairs_dev, the total into *out_count_dev.  A plan fixes the
+ * descriptors, owns the device workspace, spreads the batches over parallel
+ * branches (streams forked from and joined back into the caller's stream,
+ * largest batches first, each branch taking the next batch while it has the
+ * least work) and captures the whole fork/join of fused probe kernels once
+ * into a HIP graph; running the plan replays the graph with no host work,
+ * so new key values in the same buffers are probed at the cost of one
+ * graph launch.
+ */
+typedef struct {
+    const lj_index* index;
+    const uint64_t* s_keys_dev;
+    uint64_t m;
+    lj_pair* out_pairs_dev;   /* NULL with out_capacity 0 for count only */
+    uint64_t out_capacity;
+    uint64_t* out_count_dev;  /* receives the total (UINT64_MAX on device error) */
+} lj_batch_desc;
+
+/*
+ * Launch shape of a plan.  Batches fall in four size classes
+ * (m < 2^13, < 2^17, < 2^21, larger); a class's tiles hold
+ * 256 * keys_per_lane[class] outer keys, with keys_per_lane in
+ * {4, 8, 16, 24} (24 is lowered to 16 for indexes with duplicate keys).
+ * `branches` (1..16) is the number of parallel streams the batches are
+ * spread over; `use_graph` selects graph replay (1) or direct launches (0).
+ * `measured_ms` is filled by lj_batch_autotune.
+ */
+typedef struct {
+    uint32_t keys_per_lane[4];
+    uint32_t branches;
+    uint32_t use_graph;
+    float measured_ms;
+} lj_batch_tuning;
+
+typedef struct lj_batch_plan lj_batch_plan;
+
+/* Fill *tuning with the built-in default launch shape. */
+void lj_batch_default_tuning(lj_batch_tuning* tuning);
+
+/*
+ * Create a plan for k descriptors (k >= 1; copied, so the array may be
+ * freed).  tuning may be NULL for the default.  The indexes and buffers
+ * named by the descriptors must outlive the plan.  Synchronous.
+ * Errors: LJ_ERR_ARG (null pointer, host-only index, wrong device, bad
+ * tuning), LJ_ERR_TOO_LARGE (m >= 2^32), LJ_ERR_OOM, LJ_ERR_DEVICE.
+ */
+int lj_batch_plan_create(const lj_batch_desc* descs, uint32_t k,
+                         const lj_batch_tuning* tuning, lj_batch_plan** out_plan);
+
+/* Enqueue one run of the plan on `stream` (asynchronous; the run is ordered
+ * after earlier work on `stream` and later work waits for it).  Runs of one
+ * plan must not overlap: they share its workspace.  Errors: LJ_ERR_ARG,
+ * LJ_ERR_DEVICE. */
+int lj_batch_plan_run(lj_batch_plan* plan, hipStream_t stream);
+
+/* Free a plan (after its runs have completed).  NULL is ignored. */
+void lj_batch_plan_destroy(lj_batch_plan* plan);
+
+/*
+ * Autotuner: times candidate launch shapes (branch counts and keys per
+ * lane for each size class present) on the device with these descriptors,
+ * by coordinate descent from the default, and returns the fastest in
+ * *tuning (measured_ms = its mean time per run).  Runs the probes several
+ * times, writing the descriptors' outputs.  Synchronous.  Errors as for
+ * lj_batch_plan_create.
+ */
+int lj_batch_autotune(const lj_batch_desc* descs, uint32_t k, hipStream_t stream,
+                      lj_batch_tuning* tuning);
+
 /* Summary of an index (sizes and model quality). */
 typedef struct {
     uint64_t n;               /* keys in R */

@@ -1,0 +1,302 @@
+// Batched probe: plan objects that enqueue one fused probe kernel per batch,
+// spread over parallel branches (fork/join across streams), optionally
+// captured once into a HIP graph and replayed; and the autotuner that picks
+// their launch shape.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "lj_batch.h"
+
+struct lj_batch_plan {
+    int device = -1;
+    std::vector<lj_batch_desc> descs;
+    std::vector<uint64_t> ws_off;    // per batch workspace offset
+    std::vector<uint32_t> kpl;       // per batch keys per lane
+    std::vector<uint32_t> branch;    // per batch branch
+    void* ws = nullptr;
+    uint32_t branches = 1;
+    std::vector<hipStream_t> streams;  // one per branch
+    std::vector<hipEvent_t> join;      // one per branch
+    hipEvent_t fork = nullptr;
+    bool use_graph = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace lj {
+
+uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
+
+namespace {
+
+bool kpl_allowed(uint32_t k) { return k == 4 || k == 8 || k == 16 || k == 24; }
+
+}  // namespace
+
+int size_class(uint64_t m) {
+    if (m < (1ull << 13)) return 0;
+    if (m < (1ull << 17)) return 1;
+    if (m < (1ull << 21)) return 2;
+    return 3;
+}
+
+void default_tuning(lj_batch_tuning* t) {
+    t->keys_per_lane[0] = 4;
+    t->keys_per_lane[1] = 8;
+    t->keys_per_lane[2] = 16;
+    t->keys_per_lane[3] = 24;
+    t->branches = 4;
+    t->use_graph = 1;
+    t->measured_ms = 0.f;
+}
+
+int validate_tuning(const lj_batch_tuning& t) {
+    for (int c = 0; c < 4; ++c)
+        if (!kpl_allowed(t.keys_per_lane[c])) return LJ_ERR_ARG;
+    if (t.branches < 1 || t.branches > kMaxBranches) return LJ_ERR_ARG;
+    return LJ_OK;
+}
+
+int validate_descs(const lj_batch_desc* d, uint32_t k, int device) {
+    if (!d || k == 0) return LJ_ERR_ARG;
+    for (uint32_t b = 0; b < k; ++b) {
+        const lj_index* idx = d[b].index;
+        if (!idx || idx->host_only || idx->device != device || !d[b].out_count_dev)
+            return LJ_ERR_ARG;
+        if (d[b].m > 0 && !d[b].s_keys_dev) return LJ_ERR_ARG;
+        if (d[b].out_capacity > 0 && !d[b].out_pairs_dev) return LJ_ERR_ARG;
+        if (d[b].m >= (1ull << 32)) return LJ_ERR_TOO_LARGE;
+    }
+    return LJ_OK;
+}
+
+hipError_t enqueue_one(const lj_batch_desc& d, void* ws, uint32_t kpl, hipStream_t st) {
+    if (d.m == 0) return launch_set_u64(d.out_count_dev, 0, st);
+    if (d.index->max_mult > 1) kpl = std::min<uint32_t>(kpl, kItemsDup);
+    return launch_probe(d.index, d.s_keys_dev, d.m, d.out_pairs_dev,
+                        d.out_pairs_dev ? d.out_capacity : 0, d.out_count_dev, ws, st, nullptr,
+                        nullptr, kpl);
+}
+
+}  // namespace lj
+
+namespace {
+
+// Enqueue every batch of the plan, forked from `stream` over the branch
+// streams and joined back into it.
+hipError_t enqueue_plan(lj_batch_plan* p, hipStream_t stream) {
+    const size_t k = p->descs.size();
+    if (p->branches == 1) {
+        for (size_t b = 0; b < k; ++b) {
+            hipError_t e = lj::enqueue_one(p->descs[b], (char*)p->ws + p->ws_off[b], p->kpl[b],
+                                           stream);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    hipError_t e = hipEventRecord(p->fork, stream);
+    for (uint32_t r = 0; r < p->branches && e == hipSuccess; ++r)
+        e = hipStreamWaitEvent(p->streams[r], p->fork, 0);
+    for (size_t b = 0; b < k && e == hipSuccess; ++b)
+        e = lj::enqueue_one(p->descs[b], (char*)p->ws + p->ws_off[b], p->kpl[b],
+                            p->streams[p->branch[b]]);
+    for (uint32_t r = 0; r < p->branches && e == hipSuccess; ++r) {
+        e = hipEventRecord(p->join[r], p->streams[r]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(stream, p->join[r], 0);
+    }
+    return e;
+}
+
+int plan_create(const lj_batch_desc* descs, uint32_t k, const lj_batch_tuning* tuning,
+                lj_batch_plan** out) {
+    if (!out) return LJ_ERR_ARG;
+    *out = nullptr;
+    lj_batch_tuning t;
+    if (tuning) t = *tuning;
+    else lj::default_tuning(&t);
+    int st = lj::validate_tuning(t);
+    if (st != LJ_OK) return st;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return LJ_ERR_DEVICE;
+    st = lj::validate_descs(descs, k, dev);
+    if (st != LJ_OK) return st;
+
+    lj_batch_plan* p = new (std::nothrow) lj_batch_plan();
+    if (!p) return LJ_ERR_OOM;
+    p->device = dev;
+    p->descs.assign(descs, descs + k);
+    p->branches = std::min<uint32_t>(t.branches, k);
+    p->use_graph = t.use_graph != 0;
+
+    // Workspace slices and keys per lane.
+    uint64_t off = 0;
+    for (uint32_t b = 0; b < k; ++b) {
+        p->ws_off.push_back(off);
+        p->kpl.push_back(t.keys_per_lane[lj::size_class(descs[b].m)]);
+        off = lj::align256(off + lj::ws_bytes(descs[b].m));
+    }
+    // Longest-processing-time assignment of batches to branches.
+    std::vector<uint32_t> order(k);
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t a, uint32_t b) { return descs[a].m > descs[b].m; });
+    std::vector<uint64_t> load(p->branches, 0);
+    p->branch.assign(k, 0);
+    for (uint32_t b : order) {
+        uint32_t r = (uint32_t)(std::min_element(load.begin(), load.end()) - load.begin());
+        p->branch[b] = r;
+        load[r] += descs[b].m + 1;
+    }
+
+    hipError_t e = hipMalloc(&p->ws, std::max<uint64_t>(off, 256));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        lj_batch_plan_destroy(p);
+        return LJ_ERR_OOM;
+    }
+    if (p->branches > 1) {
+        e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+        for (uint32_t r = 0; r < p->branches && e == hipSuccess; ++r) {
+            hipStream_t s = nullptr;
+            hipEvent_t ev = nullptr;
+            e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+            if (e == hipSuccess) p->streams.push_back(s);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e == hipSuccess) p->join.push_back(ev);
+        }
+    }
+    if (e == hipSuccess && p->use_graph) {
+        hipStream_t cs = nullptr;
+        e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e == hipSuccess) {
+            e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t e1 = enqueue_plan(p, cs);
+                hipError_t e2 = hipStreamEndCapture(cs, &p->graph);
+                e = e1 != hipSuccess ? e1 : e2;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+            (void)hipStreamDestroy(cs);
+        }
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        lj_batch_plan_destroy(p);
+        return LJ_ERR_DEVICE;
+    }
+    *out = p;
+    return LJ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lj_batch_default_tuning(lj_batch_tuning* tuning) {
+    if (tuning) lj::default_tuning(tuning);
+}
+
+int lj_batch_plan_create(const lj_batch_desc* descs, uint32_t k, const lj_batch_tuning* tuning,
+                         lj_batch_plan** out_plan) {
+    try {
+        return plan_create(descs, k, tuning, out_plan);
+    } catch (const std::bad_alloc&) {
+        return LJ_ERR_OOM;
+    }
+}
+
+int lj_batch_plan_run(lj_batch_plan* p, hipStream_t stream) {
+    if (!p) return LJ_ERR_ARG;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != p->device) return LJ_ERR_ARG;
+    hipError_t e = p->use_graph ? hipGraphLaunch(p->exec, stream) : enqueue_plan(p, stream);
+    return e == hipSuccess ? LJ_OK : LJ_ERR_DEVICE;
+}
+
+void lj_batch_plan_destroy(lj_batch_plan* p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    for (hipStream_t s : p->streams) (void)hipStreamDestroy(s);
+    for (hipEvent_t ev : p->join) (void)hipEventDestroy(ev);
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    if (p->ws) (void)hipFree(p->ws);
+    delete p;
+}
+
+int lj_batch_autotune(const lj_batch_desc* descs, uint32_t k, hipStream_t stream,
+                      lj_batch_tuning* tuning) {
+    if (!tuning || !descs) return LJ_ERR_ARG;
+    bool present[4] = {false, false, false, false};
+    for (uint32_t b = 0; b < k; ++b)
+        if (descs[b].m) present[lj::size_class(descs[b].m)] = true;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return LJ_ERR_DEVICE;
+    }
+
+    // Mean time of 3 runs after one warm-up (direct launches, no graph).
+    auto measure = [&](const lj_batch_tuning& t, int* status) -> float {
+        lj_batch_tuning tt = t;
+        tt.use_graph = 0;
+        lj_batch_plan* p = nullptr;
+        *status = lj_batch_plan_create(descs, k, &tt, &p);
+        if (*status != LJ_OK) return -1.f;
+        float ms = -1.f;
+        bool ok = lj_batch_plan_run(p, stream) == LJ_OK &&
+                  hipEventRecord(e0, stream) == hipSuccess;
+        for (int r = 0; r < 3 && ok; ++r) ok = lj_batch_plan_run(p, stream) == LJ_OK;
+        ok = ok && hipEventRecord(e1, stream) == hipSuccess &&
+             hipEventSynchronize(e1) == hipSuccess &&
+             hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        if (ok) ms /= 3.f;
+        else *status = LJ_ERR_DEVICE;
+        (void)hipStreamSynchronize(stream);
+        lj_batch_plan_destroy(p);
+        return ms;
+    };
+
+    lj_batch_tuning best;
+    lj::default_tuning(&best);
+    int st = LJ_OK;
+    float best_ms = measure(best, &st);
+    // Parallel branches, then keys per lane of each size class present.
+    for (uint32_t br : {1u, 2u, 8u}) {
+        if (st != LJ_OK) break;
+        lj_batch_tuning c = best;
+        c.branches = br;
+        float ms = measure(c, &st);
+        if (st == LJ_OK && ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    for (int cl = 0; cl < 4 && st == LJ_OK; ++cl) {
+        if (!present[cl]) continue;
+        for (uint32_t kpl : {4u, 8u, 16u, 24u}) {
+            if (kpl == best.keys_per_lane[cl]) continue;
+            lj_batch_tuning c = best;
+            c.keys_per_lane[cl] = kpl;
+            float ms = measure(c, &st);
+            if (st != LJ_OK) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != LJ_OK) return st;
+    best.use_graph = 1;
+    best.measured_ms = best_ms;
+    *tuning = best;
+    return LJ_OK;
+}
+
+}  // extern "C"

@@ -46,9 +46,10 @@ constexpr int kBlock = 256;
 constexpr int kItemsUnique = 24;
 constexpr int kItemsDup = 16;
 constexpr int kSetupChunk = 4;
-constexpr int kMinTile = kBlock * 8;  // smallest tile any launch uses
+constexpr int kMinTile = kBlock * 4;  // smallest tile any launch uses
 
-// Workspace: a 256-byte header followed by one status word per tile.
+// Workspace of a single probe: a 256-byte header followed by one status
+// word per tile.
 struct WsHeader {
     uint32_t tile_counter;  // dynamic tile ids
     uint32_t done_counter;  // tiles finished
@@ -62,18 +63,46 @@ inline uint64_t num_tiles(uint64_t m, uint64_t tile) { return (m + tile - 1) / t
 // Sized for the smallest tile, so one workspace fits every launch shape.
 inline uint64_t ws_bytes(uint64_t m) { return kWsHeaderBytes + num_tiles(m, kMinTile) * 8; }
 
+// Everything the device needs to probe the tiles of one batch of outer keys
+// against one index.
+struct TileJob {
+    const uint64_t* r;
+    const void* leaves;
+    RootModel root;
+    const uint64_t* s;
+    uint64_t m;
+    lj_pair* out;
+    uint64_t cap;          // 0 when out is null
+    uint64_t* count_out;   // receives the batch's total (UINT64_MAX on error)
+    uint64_t* status;      // ntiles look-back words
+    uint32_t* done;        // tiles of this batch finished
+    uint32_t* err;         // error flag shared by the launch
+    uint32_t ntiles;
+    uint32_t kind;         // kJobFp64 | kJobDup
+    uint32_t kpl;          // keys per lane in this batch's tiles
+};
+constexpr uint32_t kJobFp64 = 1u;
+constexpr uint32_t kJobDup = 2u;
+
+inline uint32_t job_kind(const lj_index* idx) {
+    return (idx->flags == LJ_LEAF_FP64 ? kJobFp64 : 0u) | (idx->max_mult > 1 ? kJobDup : 0u);
+}
+
 // Kernel launchers (lj_kernels.hip).  Return hipSuccess or the launch error.
+// kpl: keys per lane of the launch (4, 8, 16 or, without duplicates, 24;
+// 0 = the default for the index).
+bool probe_kpl_supported(uint32_t kpl, bool dup);
 hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m,
                         lj_pair* out, uint64_t cap, uint64_t* count_dev,
                         void* ws, hipStream_t stream, hipEvent_t ev0,
-                        hipEvent_t ev1);
+                        hipEvent_t ev1, uint32_t kpl = 0);
 hipError_t launch_set_u64(uint64_t* p, uint64_t v, hipStream_t stream);
+hipError_t launch_zero_words(uint64_t* p, uint64_t nwords, hipStream_t stream);
 hipError_t launch_self_check(const lj_index* idx, uint64_t* violations_dev,
                              hipStream_t stream);
 hipError_t launch_predict_windows(const lj_index* idx, const uint64_t* keys,
                                   uint64_t m, uint32_t* leaf, int64_t* pred,
                                   int64_t* wlo, int64_t* whi, hipStream_t stream);
-
 hipError_t launch_random_gather(const void* buf, uint64_t bytes, uint32_t granule,
                                 uint64_t reads, uint64_t seed, uint64_t* sink,
                                 hipStream_t stream);

@@ -41,20 +41,6 @@ constexpr uint64_t kFlagInc = 2ull << 62;
 constexpr uint64_t kValMask = (1ull << 62) - 1;
 constexpr uint32_t kSpinLimit = 1u << 24;  // ~0.5 s of s_sleep before giving up
 
-struct ProbeParams {
-    const uint64_t* r;
-    const void* leaves;
-    RootModel root;
-    const uint64_t* s;
-    uint64_t m;
-    lj_pair* out;
-    uint64_t cap;
-    uint64_t* count_out;
-    WsHeader* hdr;
-    uint64_t* status;
-    uint32_t ntiles;
-};
-
 __device__ inline uint64_t ld_status(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -149,40 +135,44 @@ __device__ uint64_t look_back(uint64_t* status, uint32_t tile, uint64_t total,
     return excl;
 }
 
-// Last tile to finish writes the total (or UINT64_MAX after a wait error).
-__device__ void finish_tile(const ProbeParams& p) {
+// Shared memory of one tile; the duplicate path needs the per-key offsets
+// and first positions, the unique path only the per-wave counts.
+template <int kItems, bool kWithOffsets>
+struct TileShared {
+    uint64_t excl;
+    uint64_t wsum[kItems * (kBlock / 64)];
+    uint64_t off[kWithOffsets ? kBlock * kItems + 1 : 1];
+    uint32_t j0[kWithOffsets ? kBlock * kItems : 1];
+};
+
+// Last tile of a batch to finish writes the batch's total (or UINT64_MAX
+// after a wait error).
+__device__ void finish_tile(const TileJob& j) {
     if (threadIdx.x == 0) {
         __threadfence();
-        uint32_t done = atomicAdd(&p.hdr->done_counter, 1u);
-        if (done == p.ntiles - 1) {
+        uint32_t done = atomicAdd(j.done, 1u);
+        if (done == j.ntiles - 1) {
             __threadfence();
-            uint32_t e = __hip_atomic_load(&p.hdr->err, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-            uint64_t tot = ld_status(&p.status[p.ntiles - 1]) & kValMask;
-            *p.count_out = e ? ~0ull : tot;
+            uint32_t e = __hip_atomic_load(j.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t tot = ld_status(&j.status[j.ntiles - 1]) & kValMask;
+            *j.count_out = e ? ~0ull : tot;
         }
     }
 }
 
-template <class Leaf, bool kUnique, int kItems>
-__global__ __launch_bounds__(kBlock) void probe_join_kernel(ProbeParams p) {
-    __shared__ uint32_t s_tile;
-    __shared__ uint64_t s_excl;
-    __shared__ uint64_t s_wsum[kItems * (kBlock / 64)];
-    __shared__ uint64_t s_off[kUnique ? 1 : (kBlock * kItems) + 1];
-    __shared__ uint32_t s_j0[kUnique ? 1 : (kBlock * kItems)];
-
+// Probe one tile of a batch: kBlock threads, the first `kpl` (<= kItems) keys
+// of each lane are live; key k of thread t is outer key
+// tile*kBlock*kpl + k*kBlock + t.
+template <class Leaf, bool kUnique, int kItems, bool kWithOffsets>
+__device__ void probe_tile(const TileJob& j, const uint32_t tile, const uint32_t kpl,
+                           TileShared<kItems, kWithOffsets>& sh) {
+    static_assert(kUnique || kWithOffsets, "the duplicate path needs LDS offsets");
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-
-    if (tid == 0) s_tile = atomicAdd(&p.hdr->tile_counter, 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    const uint64_t tbase = (uint64_t)tile * (kBlock * kItems);
-    const Leaf* leaves = (const Leaf*)p.leaves;
-    const uint64_t* __restrict__ R = p.r;
-
+    const uint64_t tbase = (uint64_t)tile * kBlock * kpl;
+    const Leaf* leaves = (const Leaf*)j.leaves;
+    const uint64_t* __restrict__ R = j.r;
     uint64_t x[kItems];
     uint32_t first[kItems], len[kItems];
     uint32_t end[kUnique ? 1 : kItems];
@@ -195,8 +185,9 @@ __global__ __launch_bounds__(kBlock) void probe_join_kernel(ProbeParams p) {
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         uint64_t s = tbase + (uint64_t)k * kBlock + tid;
-        validmask |= (s < p.m ? 1u : 0u) << k;
-        x[k] = p.s[s < p.m ? s : p.m - 1];
+        const bool ok = (uint32_t)k < kpl && s < j.m;
+        validmask |= (ok ? 1u : 0u) << k;
+        x[k] = j.s[ok ? s : j.m - 1];
     }
     // 2: root model, leaf record, leaf model, window; kSetupChunk records
     // in flight at a time to bound register use.
@@ -204,18 +195,18 @@ __global__ __launch_bounds__(kBlock) void probe_join_kernel(ProbeParams p) {
     for (int k0 = 0; k0 < kItems; k0 += kSetupChunk) {
         Leaf lf[kSetupChunk];
 #pragma unroll
-        for (int j = 0; j < kSetupChunk; ++j) lf[j] = load_leaf(leaves + route(p.root, x[k0 + j]));
+        for (int u = 0; u < kSetupChunk; ++u) lf[u] = load_leaf(leaves + route(j.root, x[k0 + u]));
 #pragma unroll
-        for (int j = 0; j < kSetupChunk; ++j) {
-            const int k = k0 + j;
-            int64_t rel = predict_rel(lf[j], x[k]);
-            int64_t wlo = rel + lf[j].lo, whi = rel + lf[j].hi;
+        for (int u = 0; u < kSetupChunk; ++u) {
+            const int k = k0 + u;
+            int64_t rel = predict_rel(lf[u], x[k]);
+            int64_t wlo = rel + lf[u].lo, whi = rel + lf[u].hi;
             if (wlo < 0) wlo = 0;
-            if (whi > (int64_t)lf[j].cnt - 1) whi = (int64_t)lf[j].cnt - 1;
-            const bool live = ((validmask >> k) & 1u) && lf[j].cnt != 0 && wlo <= whi;
-            first[k] = live ? lf[j].pos0 + (uint32_t)wlo : 0;
+            if (whi > (int64_t)lf[u].cnt - 1) whi = (int64_t)lf[u].cnt - 1;
+            const bool live = ((validmask >> k) & 1u) && lf[u].cnt != 0 && wlo <= whi;
+            first[k] = live ? lf[u].pos0 + (uint32_t)wlo : 0;
             len[k] = live ? (uint32_t)(whi - wlo + 1) : 0;
-            if (!kUnique) end[k] = live ? lf[j].pos0 + (uint32_t)whi + 1 : 0;
+            if constexpr (!kUnique) end[k] = live ? lf[u].pos0 + (uint32_t)whi + 1 : 0;
         }
     }
 
@@ -247,7 +238,7 @@ __global__ __launch_bounds__(kBlock) void probe_join_kernel(ProbeParams p) {
     uint32_t c[kItems];
 #pragma unroll
     for (int k = 0; k < kItems; ++k) c[k] = (eqmask >> k) & 1u;
-    if (!kUnique) {
+    if constexpr (!kUnique) {
         // Forward scan of equal keys, four positions at a time, bounded by
         // the window; kSetupChunk keys per pass to bound register use.  The
         // lines read here are the ones the search just touched.
@@ -256,40 +247,40 @@ __global__ __launch_bounds__(kBlock) void probe_join_kernel(ProbeParams p) {
             uint32_t cur[kSetupChunk];
             bool act[kSetupChunk];
 #pragma unroll
-            for (int j = 0; j < kSetupChunk; ++j) {
-                cur[j] = first[k0 + j] + 1;
-                act[j] = c[k0 + j] && cur[j] < end[k0 + j];
+            for (int u = 0; u < kSetupChunk; ++u) {
+                cur[u] = first[k0 + u] + 1;
+                act[u] = c[k0 + u] && cur[u] < end[k0 + u];
             }
             for (;;) {
                 bool any = false;
 #pragma unroll
-                for (int j = 0; j < kSetupChunk; ++j) any |= act[j];
+                for (int u = 0; u < kSetupChunk; ++u) any |= act[u];
                 if (!any) break;
                 uint64_t v[kSetupChunk][4];
 #pragma unroll
-                for (int j = 0; j < kSetupChunk; ++j)
+                for (int u = 0; u < kSetupChunk; ++u)
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const bool in = act[j] && cur[j] + u < end[k0 + j];
-                        v[j][u] = R[in ? cur[j] + u : 0];
-                        if (!in) v[j][u] = ~x[k0 + j];
+                    for (int w4 = 0; w4 < 4; ++w4) {
+                        const bool in = act[u] && cur[u] + w4 < end[k0 + u];
+                        v[u][w4] = R[in ? cur[u] + w4 : 0];
+                        if (!in) v[u][w4] = ~x[k0 + u];
                     }
 #pragma unroll
-                for (int j = 0; j < kSetupChunk; ++j) {
-                    bool run = act[j];
+                for (int u = 0; u < kSetupChunk; ++u) {
+                    bool run = act[u];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        run = run && v[j][u] == x[k0 + j];
-                        c[k0 + j] += run ? 1u : 0u;
+                    for (int w4 = 0; w4 < 4; ++w4) {
+                        run = run && v[u][w4] == x[k0 + u];
+                        c[k0 + u] += run ? 1u : 0u;
                     }
-                    cur[j] += 4;
-                    act[j] = run && cur[j] < end[k0 + j];
+                    cur[u] += 4;
+                    act[u] = run && cur[u] < end[k0 + u];
                 }
             }
         }
     }
 
-    if (kUnique) {
+    if constexpr (kUnique) {
         // 5: ballot/popcount offsets; key order in the tile is (k, wave, lane).
         uint32_t lane_off[kItems];
         const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -297,35 +288,35 @@ __global__ __launch_bounds__(kBlock) void probe_join_kernel(ProbeParams p) {
         for (int k = 0; k < kItems; ++k) {
             uint64_t mask = __ballot(c[k] != 0);
             lane_off[k] = (uint32_t)__popcll(mask & lt);
-            if (lane == 0) s_wsum[k * (kBlock / 64) + wave] = (uint64_t)__popcll(mask);
+            if (lane == 0) sh.wsum[k * (kBlock / 64) + wave] = (uint64_t)__popcll(mask);
         }
         __syncthreads();
         uint64_t total = 0;
 #pragma unroll
-        for (int q = 0; q < kItems * (kBlock / 64); ++q) total += s_wsum[q];
+        for (int q = 0; q < kItems * (kBlock / 64); ++q) total += sh.wsum[q];
         // 6: look-back.
         if (wave == 0) {
-            uint64_t e = look_back(p.status, tile, total, &p.hdr->err, lane);
-            if (lane == 0) s_excl = e;
+            uint64_t e = look_back(j.status, tile, total, j.err, lane);
+            if (lane == 0) sh.excl = e;
         }
         __syncthreads();
-        const uint64_t excl = s_excl;
+        const uint64_t excl = sh.excl;
         // 7: one store per match.
-        if (p.out) {
+        if (j.out) {
             uint64_t pre = 0;
 #pragma unroll
             for (int k = 0; k < kItems; ++k) {
                 uint64_t wpre = 0;
-                for (int w = 0; w < wave; ++w) wpre += s_wsum[k * (kBlock / 64) + w];
+                for (int w = 0; w < wave; ++w) wpre += sh.wsum[k * (kBlock / 64) + w];
                 uint64_t pos = excl + pre + wpre + lane_off[k];
-                if (c[k] && pos < p.cap) {
+                if (c[k] && pos < j.cap) {
                     lj_pair pr;
                     pr.s_idx = (uint32_t)(tbase + (uint64_t)k * kBlock + tid);
                     pr.r_idx = first[k];
-                    p.out[pos] = pr;
+                    j.out[pos] = pr;
                 }
 #pragma unroll
-                for (int w = 0; w < kBlock / 64; ++w) pre += s_wsum[k * (kBlock / 64) + w];
+                for (int w = 0; w < kBlock / 64; ++w) pre += sh.wsum[k * (kBlock / 64) + w];
             }
         }
     } else {
@@ -333,8 +324,8 @@ __global__ __launch_bounds__(kBlock) void probe_join_kernel(ProbeParams p) {
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             int q = k * kBlock + tid;
-            s_off[q] = c[k];
-            s_j0[q] = first[k];
+            sh.off[q] = c[k];
+            sh.j0[q] = first[k];
         }
         __syncthreads();
         uint64_t loc[kItems];
@@ -342,47 +333,57 @@ __global__ __launch_bounds__(kBlock) void probe_join_kernel(ProbeParams p) {
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
             loc[i] = tsum;
-            tsum += s_off[tid * kItems + i];
+            tsum += sh.off[tid * kItems + i];
         }
         uint64_t incl = wave_incl_scan(tsum, lane);
-        if (lane == 63) s_wsum[wave] = incl;
+        if (lane == 63) sh.wsum[wave] = incl;
         __syncthreads();
         uint64_t wpre = 0, total = 0;
 #pragma unroll
         for (int w = 0; w < kBlock / 64; ++w) {
-            if (w < wave) wpre += s_wsum[w];
-            total += s_wsum[w];
+            if (w < wave) wpre += sh.wsum[w];
+            total += sh.wsum[w];
         }
         const uint64_t texcl = wpre + incl - tsum;
 #pragma unroll
-        for (int i = 0; i < kItems; ++i) s_off[tid * kItems + i] = texcl + loc[i];
-        if (tid == 0) s_off[(kBlock * kItems)] = total;
+        for (int i = 0; i < kItems; ++i) sh.off[tid * kItems + i] = texcl + loc[i];
+        if (tid == 0) sh.off[(kBlock * kItems)] = total;
         // 6: look-back.
         if (wave == 0) {
-            uint64_t e = look_back(p.status, tile, total, &p.hdr->err, lane);
-            if (lane == 0) s_excl = e;
+            uint64_t e = look_back(j.status, tile, total, j.err, lane);
+            if (lane == 0) sh.excl = e;
         }
         __syncthreads();
-        const uint64_t excl = s_excl;
+        const uint64_t excl = sh.excl;
         // 7: load-balanced emission of the tile's outputs.
-        if (p.out && excl < p.cap) {
-            uint64_t limit = p.cap - excl < total ? p.cap - excl : total;
+        if (j.out && excl < j.cap) {
+            uint64_t limit = j.cap - excl < total ? j.cap - excl : total;
             for (uint64_t o = tid; o < limit; o += kBlock) {
-                // last q with s_off[q] <= o
-                int lo = 0, hi = (kBlock * kItems);  // s_off[(kBlock * kItems)] = total > o
+                // last q with sh.off[q] <= o
+                int lo = 0, hi = (kBlock * kItems);  // sh.off[(kBlock * kItems)] = total > o
                 while (hi - lo > 1) {
                     int mid = (lo + hi) >> 1;
-                    if (s_off[mid] <= o) lo = mid;
+                    if (sh.off[mid] <= o) lo = mid;
                     else hi = mid;
                 }
                 lj_pair pr;
                 pr.s_idx = (uint32_t)(tbase + (uint64_t)lo);
-                pr.r_idx = s_j0[lo] + (uint32_t)(o - s_off[lo]);
-                p.out[excl + o] = pr;
+                pr.r_idx = sh.j0[lo] + (uint32_t)(o - sh.off[lo]);
+                j.out[excl + o] = pr;
             }
         }
     }
-    finish_tile(p);
+    __syncthreads();  // the block's LDS is reused by the next tile
+    finish_tile(j);
+}
+
+template <class Leaf, bool kUnique, int kItems>
+__global__ __launch_bounds__(kBlock) void probe_join_kernel(TileJob j, uint32_t* tile_counter) {
+    __shared__ uint32_t s_tile;
+    __shared__ TileShared<kItems, !kUnique> sh;
+    if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
+    __syncthreads();
+    probe_tile<Leaf, kUnique, kItems, !kUnique>(j, s_tile, kItems, sh);
 }
 
 __global__ void zero_words(uint64_t* w, uint64_t nwords) {
@@ -452,50 +453,84 @@ hipError_t launch_set_u64(uint64_t* p, uint64_t v, hipStream_t stream) {
     return hipGetLastError();
 }
 
+hipError_t launch_zero_words(uint64_t* p, uint64_t nwords, hipStream_t stream) {
+    hipLaunchKernelGGL(zero_words, dim3(grid_for(nwords, 256)), dim3(256), 0, stream, p, nwords);
+    return hipGetLastError();
+}
+
+namespace {
+
+template <int kItems>
+hipError_t launch_probe_items(const TileJob& j, uint32_t* ctr, hipStream_t stream) {
+    dim3 grid(j.ntiles), block(kBlock);
+    switch (j.kind) {
+        case 0:
+            hipLaunchKernelGGL((probe_join_kernel<LeafF32, true, kItems>), grid, block, 0, stream,
+                               j, ctr);
+            break;
+        case kJobDup:
+            if constexpr (kItems <= kItemsDup)
+                hipLaunchKernelGGL((probe_join_kernel<LeafF32, false, kItems>), grid, block, 0,
+                                   stream, j, ctr);
+            break;
+        case kJobFp64:
+            hipLaunchKernelGGL((probe_join_kernel<LeafF64, true, kItems>), grid, block, 0, stream,
+                               j, ctr);
+            break;
+        default:
+            if constexpr (kItems <= kItemsDup)
+                hipLaunchKernelGGL((probe_join_kernel<LeafF64, false, kItems>), grid, block, 0,
+                                   stream, j, ctr);
+            break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool probe_kpl_supported(uint32_t kpl, bool dup) {
+    return kpl == 4 || kpl == 8 || kpl == 16 || (!dup && kpl == 24);
+}
+
 hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m, lj_pair* out,
                         uint64_t cap, uint64_t* count_dev, void* ws, hipStream_t stream,
-                        hipEvent_t ev0, hipEvent_t ev1) {
-    const bool uniq = idx->max_mult <= 1;
-    const bool f32 = idx->flags == LJ_LEAF_FP32;
-    const uint64_t nt = num_tiles(m, kBlock * (uniq ? kItemsUnique : kItemsDup));
+                        hipEvent_t ev0, hipEvent_t ev1, uint32_t kpl) {
+    const uint32_t kind = job_kind(idx);
+    if (kpl == 0) kpl = (kind & kJobDup) ? kItemsDup : kItemsUnique;
+    if (!probe_kpl_supported(kpl, (kind & kJobDup) != 0)) return hipErrorInvalidValue;
+    const uint64_t nt = num_tiles(m, (uint64_t)kBlock * kpl);
     const uint64_t words = (kWsHeaderBytes + nt * 8) / 8;
-    hipLaunchKernelGGL(zero_words, dim3(grid_for(words, 256)), dim3(256), 0, stream,
-                       (uint64_t*)ws, words);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_zero_words((uint64_t*)ws, words, stream);
     if (e != hipSuccess) return e;
 
-    ProbeParams p;
-    p.r = idx->r_dev;
-    p.leaves = idx->leaf_dev;
-    p.root = idx->root;
-    p.s = s;
-    p.m = m;
-    p.out = out;
-    p.cap = out ? cap : 0;
-    p.count_out = count_dev;
-    p.hdr = (WsHeader*)ws;
-    p.status = (uint64_t*)((char*)ws + kWsHeaderBytes);
-    p.ntiles = (uint32_t)nt;
-
+    WsHeader* hdr = (WsHeader*)ws;
+    TileJob j;
+    j.r = idx->r_dev;
+    j.leaves = idx->leaf_dev;
+    j.root = idx->root;
+    j.s = s;
+    j.m = m;
+    j.out = out;
+    j.cap = out ? cap : 0;
+    j.count_out = count_dev;
+    j.status = (uint64_t*)((char*)ws + kWsHeaderBytes);
+    j.done = &hdr->done_counter;
+    j.err = &hdr->err;
+    j.ntiles = (uint32_t)nt;
+    j.kind = kind;
+    j.kpl = kpl;
 
     if (ev0) {
         e = hipEventRecord(ev0, stream);
         if (e != hipSuccess) return e;
     }
-    dim3 grid((unsigned)nt), block(kBlock);
-    if (f32 && uniq)
-        hipLaunchKernelGGL((probe_join_kernel<LeafF32, true, kItemsUnique>), grid, block, 0,
-                           stream, p);
-    else if (f32)
-        hipLaunchKernelGGL((probe_join_kernel<LeafF32, false, kItemsDup>), grid, block, 0,
-                           stream, p);
-    else if (uniq)
-        hipLaunchKernelGGL((probe_join_kernel<LeafF64, true, kItemsUnique>), grid, block, 0,
-                           stream, p);
-    else
-        hipLaunchKernelGGL((probe_join_kernel<LeafF64, false, kItemsDup>), grid, block, 0,
-                           stream, p);
-    e = hipGetLastError();
+    uint32_t* ctr = &hdr->tile_counter;
+    switch (kpl) {
+        case 4: e = launch_probe_items<4>(j, ctr, stream); break;
+        case 8: e = launch_probe_items<8>(j, ctr, stream); break;
+        case 16: e = launch_probe_items<16>(j, ctr, stream); break;
+        default: e = launch_probe_items<24>(j, ctr, stream); break;
+    }
     if (e != hipSuccess) return e;
     if (ev1) e = hipEventRecord(ev1, stream);
     return e;

@@ -33,7 +33,8 @@ EXPORTED = (
     "lj_build_rmi", "lj_free_index", "lj_probe_join", "lj_probe_workspace_bytes",
     "lj_probe_join_async", "lj_index_get_stats", "lj_self_check", "lj_predict_windows",
     "lj_predict_windows_host", "lj_build_rmi_host_only", "lj_probe_set_timing_events",
-    "lj_bench_random_gather", "lj_strerror",
+    "lj_bench_random_gather", "lj_strerror", "lj_batch_default_tuning",
+    "lj_batch_plan_create", "lj_batch_plan_run", "lj_batch_plan_destroy", "lj_batch_autotune",
 )
 
 
@@ -58,6 +59,30 @@ class lj_index_stats(ctypes.Structure):
         ("root_b0", ctypes.c_double),
         ("root_kmin", ctypes.c_uint64),
     ]
+
+
+class lj_batch_desc(ctypes.Structure):
+    _fields_ = [
+        ("index", ctypes.c_void_p),
+        ("s_keys_dev", ctypes.c_void_p),
+        ("m", ctypes.c_uint64),
+        ("out_pairs_dev", ctypes.c_void_p),
+        ("out_capacity", ctypes.c_uint64),
+        ("out_count_dev", ctypes.c_void_p),
+    ]
+
+
+class lj_batch_tuning(ctypes.Structure):
+    _fields_ = [
+        ("keys_per_lane", ctypes.c_uint32 * 4),
+        ("branches", ctypes.c_uint32),
+        ("use_graph", ctypes.c_uint32),
+        ("measured_ms", ctypes.c_float),
+    ]
+
+    def as_dict(self):
+        return {"keys_per_lane": list(self.keys_per_lane), "branches": self.branches,
+                "use_graph": self.use_graph, "measured_ms": self.measured_ms}
 
 
 _lib = None
@@ -87,12 +112,22 @@ def lib() -> ctypes.CDLL:
         L.lj_predict_windows_host.argtypes = [vp, vp, u64, vp, vp, vp, vp]
         L.lj_probe_set_timing_events.argtypes = [vp, vp]
         L.lj_bench_random_gather.argtypes = [vp, u64, u32, u64, u64, vp, vp]
+        L.lj_batch_default_tuning.argtypes = [ctypes.POINTER(lj_batch_tuning)]
+        L.lj_batch_default_tuning.restype = None
+        L.lj_batch_plan_create.argtypes = [ctypes.POINTER(lj_batch_desc), u32,
+                                           ctypes.POINTER(lj_batch_tuning), ctypes.POINTER(vp)]
+        L.lj_batch_plan_run.argtypes = [vp, vp]
+        L.lj_batch_plan_destroy.argtypes = [vp]
+        L.lj_batch_plan_destroy.restype = None
+        L.lj_batch_autotune.argtypes = [ctypes.POINTER(lj_batch_desc), u32, vp,
+                                        ctypes.POINTER(lj_batch_tuning)]
         L.lj_strerror.argtypes = [i32]
         L.lj_strerror.restype = ctypes.c_char_p
         for f in ("lj_build_rmi", "lj_build_rmi_host_only", "lj_probe_join",
                   "lj_probe_join_async", "lj_index_get_stats", "lj_self_check",
                   "lj_predict_windows", "lj_predict_windows_host",
-                  "lj_probe_set_timing_events", "lj_bench_random_gather"):
+                  "lj_probe_set_timing_events", "lj_bench_random_gather",
+                  "lj_batch_plan_create", "lj_batch_plan_run", "lj_batch_autotune"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -142,9 +177,9 @@ class Index:
         self.close()
 
     def close(self):
-        if getattr(self, "handle", None):
-            lib().lj_free_index(self.handle)
-            self.handle = None
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.lj_free_index(self.handle)
+        self.handle = None
 
     @property
     def stats(self) -> lj_index_stats:
@@ -245,6 +280,56 @@ def lj_bench_random_gather(buf_dev, granule: int, reads: int, seed: int, sink_de
     _check(lib().lj_bench_random_gather(_dev_ptr(buf_dev), nbytes, granule, reads, seed,
                                         _dev_ptr(sink_dev), _stream_ptr(stream)),
            "lj_bench_random_gather")
+
+
+def make_batch_descs(batches):
+    """batches: list of (Index, s_keys_dev, out_pairs_dev or None, count_dev)."""
+    arr = (lj_batch_desc * len(batches))()
+    for i, (ix, s, out, cnt) in enumerate(batches):
+        arr[i].index = ix.handle
+        arr[i].s_keys_dev = _dev_ptr(s) if s.numel() else None
+        arr[i].m = s.numel()
+        arr[i].out_pairs_dev = _dev_ptr(out) if out is not None and out.shape[0] else None
+        arr[i].out_capacity = 0 if out is None else out.shape[0]
+        arr[i].out_count_dev = _dev_ptr(cnt)
+    return arr
+
+
+def lj_batch_default_tuning() -> lj_batch_tuning:
+    t = lj_batch_tuning()
+    lib().lj_batch_default_tuning(ctypes.byref(t))
+    return t
+
+
+class BatchPlan:
+    """Owner of an lj_batch_plan handle (keeps its descriptor inputs alive)."""
+
+    def __init__(self, batches, tuning: lj_batch_tuning | None = None):
+        self._batches = batches
+        descs = make_batch_descs(batches)
+        h = ctypes.c_void_p()
+        _check(lib().lj_batch_plan_create(descs, len(batches),
+                                          ctypes.byref(tuning) if tuning is not None else None,
+                                          ctypes.byref(h)), "lj_batch_plan_create")
+        self.handle = h.value
+
+    def run(self, stream=None) -> None:
+        _check(lib().lj_batch_plan_run(self.handle, _stream_ptr(stream)), "lj_batch_plan_run")
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.lj_batch_plan_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+def lj_batch_autotune(batches, stream=None) -> lj_batch_tuning:
+    t = lj_batch_tuning()
+    _check(lib().lj_batch_autotune(make_batch_descs(batches), len(batches),
+                                   _stream_ptr(stream), ctypes.byref(t)), "lj_batch_autotune")
+    return t
 
 
 # ---------------------------------------------------------------------------

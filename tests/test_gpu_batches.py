@@ -1,0 +1,130 @@
+"""GPU parity of the batched probe (many indexes in one plan: fused probe
+kernels forked over parallel streams, replayed from a HIP graph) against the
+oracle, batch by batch."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from paper_2111_08824_amd import lj
+
+pytestmark = pytest.mark.gpu
+
+
+def _mixed_batches(seed=7):
+    """Indexes of every kind (FP32/FP64 leaves, unique/duplicate keys) and
+    batch sizes from empty to several tiles of every size class."""
+    import torch
+    ws = workloads.multi_index_batches(k=10, seed=seed, n_lo=1e3, n_hi=3e5, m_lo=1, m_hi=3e5)
+    dup = workloads.c3_dup_runs(seed=seed, scale=0.002)
+    ws.append(dup)
+    items = []
+    for i, w in enumerate(ws):
+        flags = lj.LJ_LEAF_FP64 if i % 3 == 1 else lj.LJ_LEAF_FP32
+        S = w.S if i != 4 else w.S[:0]  # one empty batch
+        ix = lj.lj_build_rmi(w.R, w.leaves, flags)
+        cap = max(1, len(S) * int(ix.stats.max_mult))
+        s = lj.to_device_keys(S)
+        out = torch.full((cap, 2), -1, dtype=torch.int32, device="cuda")
+        cnt = torch.full((1,), -7, dtype=torch.int64, device="cuda")
+        items.append((w.R, S, ix, s, out, cnt))
+    return items
+
+
+def _check(items):
+    for R, S, ix, s, out, cnt in items:
+        want = oracle.sort_merge_join(R, S)
+        got_n = int(cnt.item())
+        assert got_n == len(want), (len(R), len(S), got_n, len(want))
+        got = out[:got_n].cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_plan_matches_oracle_on_every_replay(use_graph):
+    import torch
+    items = _mixed_batches()
+    t = lj.lj_batch_default_tuning()
+    t.use_graph = use_graph
+    plan = lj.BatchPlan([(ix, s, out, cnt) for _, _, ix, s, out, cnt in items], t)
+    for rep in range(3):
+        print(f"[batches] replay {rep} graph={use_graph}", flush=True)
+        for *_, out, cnt in items:  # eager work between replays
+            out.fill_(-1)
+            cnt.fill_(-7)
+        plan.run()
+        torch.cuda.synchronize()
+        _check(items)
+    plan.close()
+
+
+def test_plan_sees_new_key_values():
+    import torch
+    items = _mixed_batches(seed=8)
+    plan = lj.BatchPlan([(ix, s, out, cnt) for _, _, ix, s, out, cnt in items])
+    plan.run()
+    torch.cuda.synchronize()
+    _check(items)
+    # overwrite the outer keys in place and replay the same graph
+    new_items = []
+    for j, (R, S, ix, s, out, cnt) in enumerate(items):
+        if len(S):
+            S2 = workloads.gen.probe_mix(R, len(S), 0.3, 100 + j, miss_hi=int(R[-1]) + 10)
+            s.copy_(lj.to_device_keys(S2))
+            S = S2
+        new_items.append((R, S, ix, s, out, cnt))
+    plan.run()
+    torch.cuda.synchronize()
+    _check(new_items)
+
+
+def test_capacity_in_a_batch():
+    import torch
+    w = workloads.c3_dup_runs(scale=0.001)
+    want = oracle.sort_merge_join(w.R, w.S)
+    ix = lj.lj_build_rmi(w.R, w.leaves)
+    s = lj.to_device_keys(w.S)
+    cap = len(want) // 2
+    out = torch.full((cap, 2), -1, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    cnt2 = torch.zeros(1, dtype=torch.int64, device="cuda")
+    plan = lj.BatchPlan([(ix, s, out, cnt), (ix, s, None, cnt2)])
+    plan.run()
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == len(want) and int(cnt2.item()) == len(want)
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), want[:cap])
+
+
+def test_autotune_then_plan():
+    import torch
+    items = _mixed_batches(seed=9)
+    batches = [(ix, s, out, cnt) for _, _, ix, s, out, cnt in items]
+    t = lj.lj_batch_autotune(batches)
+    print("[batches] tuned", t.as_dict(), flush=True)
+    assert t.measured_ms > 0
+    assert all(k in (4, 8, 16, 24) for k in t.keys_per_lane)
+    assert 1 <= t.branches <= 16
+    plan = lj.BatchPlan(batches, t)
+    for *_, out, cnt in items:
+        out.fill_(-1)
+        cnt.fill_(-7)
+    plan.run()
+    torch.cuda.synchronize()
+    _check(items)
+
+
+def test_plan_argument_errors():
+    import torch
+    w = workloads.c1_uniform(scale=0.01)
+    ix = lj.lj_build_rmi(w.R, w.leaves)
+    s = lj.to_device_keys(w.S)
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    host = lj.lj_build_rmi_host_only(w.R, w.leaves)
+    with pytest.raises(lj.LJError) as e:
+        lj.BatchPlan([(host, s, None, cnt)])
+    assert e.value.status == lj.LJ_ERR_ARG
+    t = lj.lj_batch_default_tuning()
+    t.keys_per_lane[2] = 12
+    with pytest.raises(lj.LJError) as e:
+        lj.BatchPlan([(ix, s, None, cnt)], t)
+    assert e.value.status == lj.LJ_ERR_ARG

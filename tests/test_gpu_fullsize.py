@@ -48,3 +48,49 @@ def test_lognormal_zipf_200m_full_size():
     emitted = si[pos_c] == sample
     assert np.array_equal(emitted, count == 1)
     assert np.array_equal(ri[pos_c][emitted], first[emitted].astype(np.int64))
+
+
+def test_dup_runs_100m_full_size():
+    """1e8 rows of seq_h values repeated U{1..16} times, 1e8 outer keys with
+    70% hits: about 6e8 pairs.  Exact by: every pair matches, pairs strictly
+    increase in (s, r), and their number equals the count invariant
+    sum_k mult_R(k) * mult_S(k) (numpy unique counts, independent of both the
+    GPU path and the oracle's merge); plus 100,000 sampled keys against the
+    oracle's equal_range."""
+    import torch
+    print("[fullsize] generating dup-runs-100M", flush=True)
+    w = workloads.c3_dup_runs()
+    ur, cr = np.unique(w.R, return_counts=True)
+    us, cs = np.unique(w.S, return_counts=True)
+    _, ir, is_ = np.intersect1d(ur, us, assume_unique=True, return_indices=True)
+    want = int(np.sum(cr[ir].astype(np.int64) * cs[is_].astype(np.int64)))
+    del ur, cr, us, cs
+    print(f"[fullsize] building index (fp32 leaves, {w.leaves}); expecting {want} pairs",
+          flush=True)
+    ix = lj.lj_build_rmi(w.R, w.leaves, lj.LJ_LEAF_FP32)
+    assert lj.lj_self_check(ix) == 0
+    s = lj.to_device_keys(w.S)
+    out = torch.empty((want, 2), dtype=torch.int32, device="cuda")
+    st, cnt = lj.lj_probe_join(ix, s, out)
+    assert st == lj.LJ_OK and cnt == want
+    P = out.cpu().numpy().view(np.uint32)
+    del out, s
+    chunk = 50_000_000
+    prev = -1
+    for a in range(0, cnt, chunk):
+        b = min(cnt, a + chunk)
+        si = P[a:b, 0].astype(np.int64)
+        ri = P[a:b, 1].astype(np.int64)
+        key = si * (1 << 32) + ri
+        assert key[0] > prev and np.all(np.diff(key) > 0)
+        prev = int(key[-1])
+        assert np.array_equal(w.S[si], w.R[ri])
+    rng = np.random.default_rng(2)
+    sample = np.sort(rng.choice(len(w.S), 100_000, replace=False))
+    first, count = oracle.equal_range(w.R, w.S[sample])
+    s_all = P[:, 0]
+    lo = np.searchsorted(s_all, sample.astype(np.uint32), side="left")
+    hi = np.searchsorted(s_all, sample.astype(np.uint32), side="right")
+    assert np.array_equal(hi - lo, count.astype(np.int64))
+    hit = count > 0
+    assert np.array_equal(P[lo[hit], 1].astype(np.int64), first[hit].astype(np.int64))
