@@ -51,7 +51,8 @@ enum {
     LJ_ERR_CAPACITY = -4,  /* more pairs than out_capacity (count still set) */
     LJ_ERR_DEVICE = -5,    /* a HIP call failed, or a kernel reported an error */
     LJ_ERR_OOM = -6,       /* device or host allocation failed */
-    LJ_ERR_WORKSPACE = -7  /* workspace smaller than lj_probe_workspace_bytes(m) */
+    LJ_ERR_WORKSPACE = -7, /* workspace smaller than lj_probe_workspace_bytes(m) */
+    LJ_ERR_TIMEOUT = -8    /* a wait ended before the request completed */
 };
 
 /* Leaf-model arithmetic.  Exactly one must be given to lj_build_rmi. */
@@ -215,6 +216,89 @@ void lj_batch_plan_destroy(lj_batch_plan* plan);
  */
 int lj_batch_autotune(const lj_batch_desc* descs, uint32_t k, hipStream_t stream,
                       lj_batch_tuning* tuning);
+
+/*
+ * Serving loop: several indexes resident in HBM, probe requests admitted by
+ * memory and batched continuously.
+ *
+ * Requests carry host buffers: the server copies the outer keys to the
+ * device, probes, and copies the pairs back.  A scheduler thread admits
+ * requests in arrival order while the head request's device footprint
+ * (keys + output + workspace) fits the memory budget left, forms a batch as
+ * soon as one of `slots` streams is free (so requests that arrive while
+ * others run join the next batch), and enqueues the batch's copies and
+ * fused probes on that stream; batches on different streams overlap on the
+ * device.  A completion thread per stream copies results back, frees the
+ * memory and wakes the waiters.  Device memory for requests comes from one
+ * arena of `budget_bytes` allocated at creation.
+ */
+typedef struct {
+    uint64_t budget_bytes;        /* device memory for request buffers (> 0) */
+    uint32_t slots;               /* batches in flight, 1..16 */
+    uint32_t max_batch_requests;  /* requests per batch, >= 1 */
+    uint64_t max_batch_keys;      /* outer keys per batch (a larger single request
+                                     still forms a batch alone), >= 1 */
+    uint32_t keys_per_lane[4];    /* tile shape per size class, as in lj_batch_tuning */
+} lj_server_config;
+
+typedef struct lj_server lj_server;
+
+typedef struct {
+    int32_t status;        /* LJ_OK, LJ_ERR_CAPACITY (pairs truncated) or an error */
+    uint32_t batch_size;   /* requests in the batch this request ran in */
+    uint64_t count;        /* total matching pairs */
+    uint64_t submit_ns;    /* steady-clock times of submission, launch, completion */
+    uint64_t start_ns;
+    uint64_t done_ns;
+} lj_request_result;
+
+typedef struct {
+    uint64_t requests_done;
+    uint64_t batches;
+    uint64_t peak_bytes_in_use;   /* never above budget_bytes */
+    uint64_t peak_queue;          /* requests waiting for admission */
+    uint64_t max_batch_size;
+    uint64_t keys_probed;
+} lj_server_stats;
+
+/* Fill *config with defaults for a budget: 4 slots, 64 requests and 2^24
+ * keys per batch, keys per lane 4/8/16/24. */
+void lj_server_default_config(lj_server_config* config, uint64_t budget_bytes);
+
+/*
+ * Start a server over `n_indexes` indexes (not owned; they must outlive
+ * the server and live on the current device).  Allocates the arena and
+ * starts the threads.  Errors: LJ_ERR_ARG, LJ_ERR_OOM, LJ_ERR_DEVICE.
+ */
+int lj_server_create(lj_index* const* indexes, uint32_t n_indexes,
+                     const lj_server_config* config, lj_server** out_server);
+
+/*
+ * Submit a request: probe index `index_id` with the m keys at s_keys_host;
+ * up to out_capacity pairs go to out_pairs_host.  Both host buffers must
+ * stay valid until the request completes (pinned memory makes the copies
+ * asynchronous).  Returns at once with a ticket.  Errors: LJ_ERR_ARG,
+ * LJ_ERR_TOO_LARGE (m >= 2^32, or the request alone exceeds the budget:
+ * it could never be admitted).
+ */
+int lj_server_submit(lj_server* server, uint32_t index_id, const uint64_t* s_keys_host,
+                     uint64_t m, lj_pair* out_pairs_host, uint64_t out_capacity,
+                     uint64_t* out_ticket);
+
+/*
+ * Wait until a request completes (timeout_ms < 0: no limit) and fetch its
+ * result; a ticket can be waited for once.  Returns LJ_OK when the result
+ * was fetched (the request's own status is in result->status),
+ * LJ_ERR_TIMEOUT if it did not complete in time, LJ_ERR_ARG for an
+ * unknown ticket.
+ */
+int lj_server_wait(lj_server* server, uint64_t ticket, int64_t timeout_ms,
+                   lj_request_result* result);
+
+int lj_server_get_stats(lj_server* server, lj_server_stats* out);
+
+/* Finish every submitted request, stop the threads and free the arena. */
+void lj_server_destroy(lj_server* server);
 
 /* Summary of an index (sizes and model quality). */
 typedef struct {

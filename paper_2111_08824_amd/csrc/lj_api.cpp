@@ -315,6 +315,7 @@ const char* lj_strerror(int s) {
         case LJ_ERR_DEVICE: return "device error";
         case LJ_ERR_OOM: return "out of memory";
         case LJ_ERR_WORKSPACE: return "workspace too small or misaligned";
+        case LJ_ERR_TIMEOUT: return "timed out";
         default: return "unknown status";
     }
 }

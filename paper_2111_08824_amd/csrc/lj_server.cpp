@@ -1,0 +1,420 @@
+// Serving loop: resident indexes, memory-budget admission, continuous
+// batching over several streams, per-request latency.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "lj_batch.h"
+
+namespace {
+
+uint64_t now_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// First-fit allocator over [0, capacity) with coalescing of freed ranges;
+// sizes are multiples of 256 bytes.
+class Arena {
+   public:
+    explicit Arena(uint64_t cap) : cap_(cap) { free_[0] = cap; }
+    bool alloc(uint64_t size, uint64_t* off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < size) continue;
+            *off = it->first;
+            uint64_t rest = it->second - size;
+            uint64_t start = it->first + size;
+            free_.erase(it);
+            if (rest) free_[start] = rest;
+            used_ += size;
+            return true;
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t size) {
+        used_ -= size;
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && off + size == next->first) {
+            size += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                prev->second += size;
+                return;
+            }
+        }
+        free_[off] = size;
+    }
+    uint64_t used() const { return used_; }
+
+   private:
+    std::map<uint64_t, uint64_t> free_;  // offset -> size
+    uint64_t cap_;
+    uint64_t used_ = 0;
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    uint32_t index_id = 0;
+    const uint64_t* s_host = nullptr;
+    uint64_t m = 0;
+    lj_pair* out_host = nullptr;
+    uint64_t cap = 0;
+    uint64_t devcap = 0;  // pairs the device buffer holds
+    uint64_t bytes = 0;   // arena footprint
+    uint64_t off = 0;     // arena offset
+    uint64_t s_off = 0, out_off = 0, ws_off = 0, cnt_off = 0;  // within the block
+    bool done = false;
+    lj_request_result res{};
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t event = nullptr;
+    uint64_t* counts_host = nullptr;  // pinned, one per request of a batch
+    std::vector<Request*> batch;
+    bool busy = false;
+    bool has_work = false;
+    std::condition_variable cv;
+    std::thread worker;
+};
+
+}  // namespace
+
+struct lj_server {
+    int device = -1;
+    std::vector<lj_index*> indexes;
+    lj_server_config cfg{};
+    char* arena_base = nullptr;
+    Arena* arena = nullptr;
+
+    std::mutex mu;
+    std::condition_variable cv_sched, cv_done;
+    std::deque<Request*> queue;
+    std::unordered_map<uint64_t, Request*> requests;
+    uint64_t next_ticket = 1;
+    bool stopping = false;
+    std::vector<Slot*> slots;
+    std::thread scheduler;
+    lj_server_stats stats{};
+
+    void schedule_loop();
+    void slot_loop(Slot* s);
+    hipError_t enqueue_batch(Slot* s);
+};
+
+namespace {
+
+uint64_t footprint(const lj_index* idx, uint64_t m, uint64_t cap, Request* r) {
+    uint64_t devcap = std::min<uint64_t>(cap, m * std::max<uint64_t>(idx->max_mult, 1));
+    uint64_t off = 0;
+    uint64_t s_off = off;
+    off = lj::align256(off + 8 * m);
+    uint64_t out_off = off;
+    off = lj::align256(off + 8 * devcap);
+    uint64_t ws_off = off;
+    off = lj::align256(off + lj::ws_bytes(m));
+    uint64_t cnt_off = off;
+    off = lj::align256(off + 8);
+    if (r) {
+        r->devcap = devcap;
+        r->s_off = s_off;
+        r->out_off = out_off;
+        r->ws_off = ws_off;
+        r->cnt_off = cnt_off;
+        r->bytes = off;
+    }
+    return off;
+}
+
+}  // namespace
+
+hipError_t lj_server::enqueue_batch(Slot* s) {
+    hipError_t e = hipSuccess;
+    for (Request* r : s->batch) {
+        char* base = arena_base + r->off;
+        if (r->m)
+            e = hipMemcpyAsync(base + r->s_off, r->s_host, 8 * r->m, hipMemcpyHostToDevice,
+                               s->stream);
+        if (e != hipSuccess) return e;
+    }
+    for (Request* r : s->batch) {
+        char* base = arena_base + r->off;
+        lj_batch_desc d;
+        d.index = indexes[r->index_id];
+        d.s_keys_dev = (const uint64_t*)(base + r->s_off);
+        d.m = r->m;
+        d.out_pairs_dev = r->devcap ? (lj_pair*)(base + r->out_off) : nullptr;
+        d.out_capacity = r->devcap;
+        d.out_count_dev = (uint64_t*)(base + r->cnt_off);
+        e = lj::enqueue_one(d, base + r->ws_off, cfg.keys_per_lane[lj::size_class(r->m)],
+                            s->stream);
+        if (e != hipSuccess) return e;
+    }
+    for (size_t i = 0; i < s->batch.size(); ++i) {
+        Request* r = s->batch[i];
+        e = hipMemcpyAsync(&s->counts_host[i], arena_base + r->off + r->cnt_off, 8,
+                           hipMemcpyDeviceToHost, s->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipEventRecord(s->event, s->stream);
+}
+
+void lj_server::schedule_loop() {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+        Slot* free_slot = nullptr;
+        for (Slot* s : slots)
+            if (!s->busy) {
+                free_slot = s;
+                break;
+            }
+        if (stopping && queue.empty()) break;
+        if (!free_slot || queue.empty()) {
+            cv_sched.wait(lk);
+            continue;
+        }
+        // Admit requests in arrival order while the head fits the memory
+        // left and the batch limits allow.
+        std::vector<Request*> batch;
+        uint64_t keys = 0;
+        while (!queue.empty() && batch.size() < cfg.max_batch_requests) {
+            Request* r = queue.front();
+            if (!batch.empty() && keys + r->m > cfg.max_batch_keys) break;
+            if (!arena->alloc(r->bytes, &r->off)) break;
+            queue.pop_front();
+            batch.push_back(r);
+            keys += r->m;
+        }
+        stats.peak_bytes_in_use = std::max(stats.peak_bytes_in_use, arena->used());
+        if (batch.empty()) {  // the head waits for memory to be released
+            cv_sched.wait(lk);
+            continue;
+        }
+        free_slot->busy = true;
+        free_slot->batch = batch;
+        stats.batches++;
+        stats.max_batch_size = std::max<uint64_t>(stats.max_batch_size, batch.size());
+        const uint64_t t = now_ns();
+        for (Request* r : batch) {
+            r->res.start_ns = t;
+            r->res.batch_size = (uint32_t)batch.size();
+        }
+        lk.unlock();
+        hipError_t e = enqueue_batch(free_slot);
+        lk.lock();
+        if (e != hipSuccess) {
+            for (Request* r : batch) r->res.status = LJ_ERR_DEVICE;
+        }
+        free_slot->has_work = true;
+        free_slot->cv.notify_one();
+    }
+}
+
+void lj_server::slot_loop(Slot* s) {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+        s->cv.wait(lk, [&] { return s->has_work || (stopping && !s->busy); });
+        if (!s->has_work) break;
+        std::vector<Request*> batch = s->batch;
+        lk.unlock();
+        bool ok = hipEventSynchronize(s->event) == hipSuccess;
+        std::vector<uint64_t> counts(batch.size(), ~0ull);
+        for (size_t i = 0; i < batch.size() && ok; ++i) {
+            Request* r = batch[i];
+            counts[i] = s->counts_host[i];
+            if (r->res.status != LJ_OK || counts[i] == ~0ull) continue;
+            uint64_t n = std::min(counts[i], std::min(r->cap, r->devcap));
+            if (n)
+                ok = hipMemcpyAsync(r->out_host, arena_base + r->off + r->out_off,
+                                    n * sizeof(lj_pair), hipMemcpyDeviceToHost,
+                                    s->stream) == hipSuccess;
+        }
+        ok = ok && hipStreamSynchronize(s->stream) == hipSuccess;
+        const uint64_t t = now_ns();
+        lk.lock();
+        for (size_t i = 0; i < batch.size(); ++i) {
+            Request* r = batch[i];
+            if (r->res.status == LJ_OK) {
+                if (!ok || counts[i] == ~0ull) r->res.status = LJ_ERR_DEVICE;
+                else if (counts[i] > r->cap) r->res.status = LJ_ERR_CAPACITY;
+            }
+            r->res.count = counts[i];
+            r->res.done_ns = t;
+            r->done = true;
+            arena->release(r->off, r->bytes);
+            stats.requests_done++;
+            stats.keys_probed += r->m;
+        }
+        s->batch.clear();
+        s->has_work = false;
+        s->busy = false;
+        cv_done.notify_all();
+        cv_sched.notify_all();
+    }
+}
+
+extern "C" {
+
+void lj_server_default_config(lj_server_config* c, uint64_t budget_bytes) {
+    if (!c) return;
+    c->budget_bytes = budget_bytes;
+    c->slots = 4;
+    c->max_batch_requests = 64;
+    c->max_batch_keys = 1ull << 24;
+    c->keys_per_lane[0] = 4;
+    c->keys_per_lane[1] = 8;
+    c->keys_per_lane[2] = 16;
+    c->keys_per_lane[3] = 24;
+}
+
+int lj_server_create(lj_index* const* indexes, uint32_t n, const lj_server_config* cfg,
+                     lj_server** out) {
+    if (!out) return LJ_ERR_ARG;
+    *out = nullptr;
+    if (!indexes || n == 0 || !cfg || cfg->budget_bytes == 0 || cfg->slots < 1 ||
+        cfg->slots > 16 || cfg->max_batch_requests < 1 || cfg->max_batch_keys < 1)
+        return LJ_ERR_ARG;
+    lj_batch_tuning t;
+    lj::default_tuning(&t);
+    for (int c = 0; c < 4; ++c) t.keys_per_lane[c] = cfg->keys_per_lane[c];
+    if (lj::validate_tuning(t) != LJ_OK) return LJ_ERR_ARG;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return LJ_ERR_DEVICE;
+    for (uint32_t i = 0; i < n; ++i)
+        if (!indexes[i] || indexes[i]->host_only || indexes[i]->device != dev) return LJ_ERR_ARG;
+
+    lj_server* sv = new (std::nothrow) lj_server();
+    if (!sv) return LJ_ERR_OOM;
+    sv->device = dev;
+    sv->indexes.assign(indexes, indexes + n);
+    sv->cfg = *cfg;
+    sv->cfg.budget_bytes = cfg->budget_bytes & ~255ull;
+    int st = LJ_OK;
+    if (hipMalloc((void**)&sv->arena_base, sv->cfg.budget_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        st = LJ_ERR_OOM;
+    }
+    for (uint32_t i = 0; i < cfg->slots && st == LJ_OK; ++i) {
+        Slot* s = new (std::nothrow) Slot();
+        if (!s) {
+            st = LJ_ERR_OOM;
+            break;
+        }
+        sv->slots.push_back(s);
+        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&s->event, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc((void**)&s->counts_host, 8ull * cfg->max_batch_requests) !=
+                hipSuccess)
+            st = LJ_ERR_DEVICE;
+    }
+    if (st != LJ_OK) {
+        lj_server_destroy(sv);
+        return st;
+    }
+    sv->arena = new Arena(sv->cfg.budget_bytes);
+    for (Slot* s : sv->slots) s->worker = std::thread(&lj_server::slot_loop, sv, s);
+    sv->scheduler = std::thread(&lj_server::schedule_loop, sv);
+    *out = sv;
+    return LJ_OK;
+}
+
+int lj_server_submit(lj_server* sv, uint32_t index_id, const uint64_t* s_host, uint64_t m,
+                     lj_pair* out_host, uint64_t cap, uint64_t* ticket) {
+    if (!sv || !ticket || index_id >= sv->indexes.size()) return LJ_ERR_ARG;
+    if ((m && !s_host) || (cap && !out_host)) return LJ_ERR_ARG;
+    if (m >= (1ull << 32)) return LJ_ERR_TOO_LARGE;
+    Request* r = new (std::nothrow) Request();
+    if (!r) return LJ_ERR_OOM;
+    r->index_id = index_id;
+    r->s_host = s_host;
+    r->m = m;
+    r->out_host = out_host;
+    r->cap = out_host ? cap : 0;
+    footprint(sv->indexes[index_id], m, r->cap, r);
+    if (r->bytes > sv->cfg.budget_bytes) {
+        delete r;
+        return LJ_ERR_TOO_LARGE;
+    }
+    r->res.status = LJ_OK;
+    r->res.submit_ns = now_ns();
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stopping) {
+        delete r;
+        return LJ_ERR_ARG;
+    }
+    r->ticket = sv->next_ticket++;
+    sv->requests[r->ticket] = r;
+    sv->queue.push_back(r);
+    sv->stats.peak_queue = std::max<uint64_t>(sv->stats.peak_queue, sv->queue.size());
+    *ticket = r->ticket;
+    sv->cv_sched.notify_all();
+    return LJ_OK;
+}
+
+int lj_server_wait(lj_server* sv, uint64_t ticket, int64_t timeout_ms, lj_request_result* res) {
+    if (!sv || !res) return LJ_ERR_ARG;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto it = sv->requests.find(ticket);
+    if (it == sv->requests.end()) return LJ_ERR_ARG;
+    Request* r = it->second;
+    if (timeout_ms < 0) {
+        sv->cv_done.wait(lk, [&] { return r->done; });
+    } else if (!sv->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms),
+                                     [&] { return r->done; })) {
+        return LJ_ERR_TIMEOUT;
+    }
+    *res = r->res;
+    sv->requests.erase(ticket);
+    delete r;
+    return LJ_OK;
+}
+
+int lj_server_get_stats(lj_server* sv, lj_server_stats* out) {
+    if (!sv || !out) return LJ_ERR_ARG;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    *out = sv->stats;
+    return LJ_OK;
+}
+
+void lj_server_destroy(lj_server* sv) {
+    if (!sv) return;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stopping = true;
+        sv->cv_sched.notify_all();
+        for (Slot* s : sv->slots) s->cv.notify_all();
+    }
+    if (sv->scheduler.joinable()) sv->scheduler.join();
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        for (Slot* s : sv->slots) s->cv.notify_all();
+    }
+    for (Slot* s : sv->slots) {
+        if (s->worker.joinable()) s->worker.join();
+        if (s->stream) (void)hipStreamDestroy(s->stream);
+        if (s->event) (void)hipEventDestroy(s->event);
+        if (s->counts_host) (void)hipHostFree(s->counts_host);
+        delete s;
+    }
+    for (auto& kv : sv->requests) delete kv.second;
+    if (sv->arena_base) (void)hipFree(sv->arena_base);
+    delete sv->arena;
+    delete sv;
+}
+
+}  // extern "C"

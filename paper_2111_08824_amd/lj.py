@@ -25,6 +25,7 @@ LJ_ERR_CAPACITY = -4
 LJ_ERR_DEVICE = -5
 LJ_ERR_OOM = -6
 LJ_ERR_WORKSPACE = -7
+LJ_ERR_TIMEOUT = -8
 
 LJ_LEAF_FP32 = 1
 LJ_LEAF_FP64 = 2
@@ -35,6 +36,8 @@ EXPORTED = (
     "lj_predict_windows_host", "lj_build_rmi_host_only", "lj_probe_set_timing_events",
     "lj_bench_random_gather", "lj_strerror", "lj_batch_default_tuning",
     "lj_batch_plan_create", "lj_batch_plan_run", "lj_batch_plan_destroy", "lj_batch_autotune",
+    "lj_server_default_config", "lj_server_create", "lj_server_submit", "lj_server_wait",
+    "lj_server_get_stats", "lj_server_destroy",
 )
 
 
@@ -85,6 +88,38 @@ class lj_batch_tuning(ctypes.Structure):
                 "use_graph": self.use_graph, "measured_ms": self.measured_ms}
 
 
+class lj_server_config(ctypes.Structure):
+    _fields_ = [
+        ("budget_bytes", ctypes.c_uint64),
+        ("slots", ctypes.c_uint32),
+        ("max_batch_requests", ctypes.c_uint32),
+        ("max_batch_keys", ctypes.c_uint64),
+        ("keys_per_lane", ctypes.c_uint32 * 4),
+    ]
+
+
+class lj_request_result(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("batch_size", ctypes.c_uint32),
+        ("count", ctypes.c_uint64),
+        ("submit_ns", ctypes.c_uint64),
+        ("start_ns", ctypes.c_uint64),
+        ("done_ns", ctypes.c_uint64),
+    ]
+
+
+class lj_server_stats(ctypes.Structure):
+    _fields_ = [
+        ("requests_done", ctypes.c_uint64),
+        ("batches", ctypes.c_uint64),
+        ("peak_bytes_in_use", ctypes.c_uint64),
+        ("peak_queue", ctypes.c_uint64),
+        ("max_batch_size", ctypes.c_uint64),
+        ("keys_probed", ctypes.c_uint64),
+    ]
+
+
 _lib = None
 
 
@@ -121,13 +156,24 @@ def lib() -> ctypes.CDLL:
         L.lj_batch_plan_destroy.restype = None
         L.lj_batch_autotune.argtypes = [ctypes.POINTER(lj_batch_desc), u32, vp,
                                         ctypes.POINTER(lj_batch_tuning)]
+        L.lj_server_default_config.argtypes = [ctypes.POINTER(lj_server_config), u64]
+        L.lj_server_default_config.restype = None
+        L.lj_server_create.argtypes = [ctypes.POINTER(vp), u32, ctypes.POINTER(lj_server_config),
+                                       ctypes.POINTER(vp)]
+        L.lj_server_submit.argtypes = [vp, u32, vp, u64, vp, u64, ctypes.POINTER(u64)]
+        L.lj_server_wait.argtypes = [vp, u64, ctypes.c_int64, ctypes.POINTER(lj_request_result)]
+        L.lj_server_get_stats.argtypes = [vp, ctypes.POINTER(lj_server_stats)]
+        L.lj_server_destroy.argtypes = [vp]
+        L.lj_server_destroy.restype = None
         L.lj_strerror.argtypes = [i32]
         L.lj_strerror.restype = ctypes.c_char_p
         for f in ("lj_build_rmi", "lj_build_rmi_host_only", "lj_probe_join",
                   "lj_probe_join_async", "lj_index_get_stats", "lj_self_check",
                   "lj_predict_windows", "lj_predict_windows_host",
                   "lj_probe_set_timing_events", "lj_bench_random_gather",
-                  "lj_batch_plan_create", "lj_batch_plan_run", "lj_batch_autotune"):
+                  "lj_batch_plan_create", "lj_batch_plan_run", "lj_batch_autotune",
+                  "lj_server_create", "lj_server_submit", "lj_server_wait",
+                  "lj_server_get_stats"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -330,6 +376,58 @@ def lj_batch_autotune(batches, stream=None) -> lj_batch_tuning:
     _check(lib().lj_batch_autotune(make_batch_descs(batches), len(batches),
                                    _stream_ptr(stream), ctypes.byref(t)), "lj_batch_autotune")
     return t
+
+
+def lj_server_default_config(budget_bytes: int) -> lj_server_config:
+    c = lj_server_config()
+    lib().lj_server_default_config(ctypes.byref(c), budget_bytes)
+    return c
+
+
+class Server:
+    """Owner of an lj_server handle.  Host buffers passed to submit() must
+    stay alive until wait() returns for that ticket (numpy arrays, ideally
+    backed by pinned memory)."""
+
+    def __init__(self, indexes, config: lj_server_config):
+        self._indexes = list(indexes)
+        arr = (ctypes.c_void_p * len(indexes))(*[ix.handle for ix in indexes])
+        h = ctypes.c_void_p()
+        _check(lib().lj_server_create(arr, len(indexes), ctypes.byref(config), ctypes.byref(h)),
+               "lj_server_create")
+        self.handle = h.value
+
+    def submit(self, index_id: int, s_keys_host: np.ndarray, out_pairs_host) -> int:
+        """out_pairs_host: uint32 array of shape (cap, 2), or None."""
+        assert s_keys_host.dtype == np.uint64 and s_keys_host.flags["C_CONTIGUOUS"]
+        cap = 0 if out_pairs_host is None else out_pairs_host.shape[0]
+        t = ctypes.c_uint64()
+        _check(lib().lj_server_submit(self.handle, index_id,
+                                      s_keys_host.ctypes.data if len(s_keys_host) else None,
+                                      len(s_keys_host),
+                                      out_pairs_host.ctypes.data if cap else None, cap,
+                                      ctypes.byref(t)), "lj_server_submit")
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> lj_request_result:
+        r = lj_request_result()
+        _check(lib().lj_server_wait(self.handle, ticket, timeout_ms, ctypes.byref(r)),
+               "lj_server_wait")
+        return r
+
+    @property
+    def stats(self) -> lj_server_stats:
+        s = lj_server_stats()
+        _check(lib().lj_server_get_stats(self.handle, ctypes.byref(s)), "lj_server_get_stats")
+        return s
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.lj_server_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        self.close()
 
 
 # ---------------------------------------------------------------------------
