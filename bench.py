@@ -102,6 +102,201 @@ def cpu_baseline(w, sample: int):
                       f"{len(w.R)} inner keys ({len(P)} pairs) in {dt:.2f} s, one thread"}
 
 
+def _json_line(res: dict) -> None:
+    print(json.dumps(res), flush=True)
+
+
+def bench_multi_index(args) -> None:
+    """64 independent indexes, one batch of outer keys each: the plain probe
+    launched batch after batch (synchronous, as a caller would without the
+    batched API) against one autotuned plan replayed from a HIP graph."""
+    import torch
+    import workloads
+    from paper_2111_08824_amd import lj
+
+    t0 = time.perf_counter()
+    ws = workloads.multi_index_batches(k=64)
+    print(f"[bench] generated 64 indexes, {sum(len(w.R) for w in ws)} inner and "
+          f"{sum(len(w.S) for w in ws)} outer keys ({time.perf_counter() - t0:.1f} s)",
+          file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    batches, expected = [], []
+    for w in ws:
+        ix = lj.lj_build_rmi(w.R, w.leaves, lj.LJ_LEAF_FP32, stream)
+        s = lj.to_device_keys(w.S)
+        out = torch.empty((max(1, len(w.S)), 2), dtype=torch.int32, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        batches.append((ix, s, out, cnt))
+        expected.append(w.expected_count)
+    m_total = sum(len(w.S) for w in ws)
+    torch.cuda.synchronize()
+
+    def plain_once():
+        for ix, s, out, cnt in batches:
+            st, c = lj.lj_probe_join(ix, s, out, stream)
+            assert st == lj.LJ_OK
+
+    for _ in range(args.warmup):
+        plain_once()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(args.steps):
+        plain_once()
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - a) * 1e3 / args.steps
+
+    tuning = lj.lj_batch_autotune(batches, stream)
+    plan = lj.BatchPlan(batches, tuning)
+    for _ in range(args.warmup):
+        plan.run(stream)
+    torch.cuda.synchronize()
+    lat = []
+    a = time.perf_counter()
+    for _ in range(args.steps):
+        b = time.perf_counter()
+        plan.run(stream)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - b)
+    plan_ms = (time.perf_counter() - a) * 1e3 / args.steps
+    got = [int(c.item()) for *_, c in batches]
+    if got != expected:
+        raise SystemExit("batched pair counts differ from the generator's hit counts")
+    lat_ms = np.array(lat) * 1e3
+    _json_line({
+        "metric": METRIC, "value": m_total / (plan_ms * 1e-3), "unit": "probes/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(plan_ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "multi-index-64", "indexes": 64,
+                   "inner_keys": int(sum(len(w.R) for w in ws)), "outer_keys": int(m_total),
+                   "tuning": tuning.as_dict()},
+        "plain_per_batch": {"ms_per_step": round(plain_ms, 4),
+                            "probes_per_s": m_total / (plain_ms * 1e-3)},
+        "speedup_vs_plain": round(plain_ms / plan_ms, 3),
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
+                       "p99": round(float(np.percentile(lat_ms, 99)), 4)},
+        "roofline": None, "cpu_baseline": None,
+    })
+
+
+def bench_serving(args) -> None:
+    """8 resident indexes of 5e7 keys, a Poisson stream of requests of
+    256..4M keys (log-uniform) at 0.5x and 0.8x the saturation rate of the
+    plain per-request probe, run through the serving loop configured as the
+    plain per-request probe (one stream, one request per launch) and as the
+    continuously batching server (4 streams, up to 64 requests per batch)."""
+    import threading
+    import queue as pyqueue
+
+    import torch
+    import workloads
+    from paper_2111_08824_amd import lj
+
+    t0 = time.perf_counter()
+    ws = workloads.resident_indexes()
+    ixs = [lj.lj_build_rmi(w.R, w.leaves, lj.LJ_LEAF_FP32) for w in ws]
+    print(f"[bench] 8 resident indexes ready ({time.perf_counter() - t0:.1f} s)",
+          file=sys.stderr, flush=True)
+    rng = np.random.default_rng(7)
+    max_m = 4 << 20
+    nreq = args.requests
+
+    def make_requests(n):
+        out = []
+        for _ in range(n):
+            i = int(rng.integers(0, len(ws)))
+            m = int(np.exp(rng.uniform(np.log(256), np.log(max_m))))
+            a = int(rng.integers(0, len(ws[i].S) - m))
+            out.append((i, a, m))
+        return out
+
+    # Outer-key pools in pinned host memory (requests are views into them) and
+    # a ring of pinned output buffers.
+    pool = len(ws[0].S)
+    pin_s = torch.empty((len(ws), pool), dtype=torch.int64, pin_memory=True)
+    s_np = pin_s.numpy().view(np.uint64)
+    for i, w in enumerate(ws):
+        s_np[i] = w.S
+    nbuf = 32
+    pin_o = torch.empty((nbuf, max_m, 2), dtype=torch.int32, pin_memory=True)
+    o_np = pin_o.numpy().view(np.uint32)
+
+    def run(cfg, reqs, rate):
+        """Submit reqs (Poisson arrivals at `rate` per second, or all at once
+        when rate is None); returns (wall seconds, latencies in ms)."""
+        srv = lj.Server(ixs, cfg)
+        free = pyqueue.Queue()
+        for b in range(nbuf):
+            free.put(b)
+        tickets = pyqueue.Queue()
+        lat = []
+
+        def collector():
+            for _ in range(len(reqs)):
+                t, b, m = tickets.get()
+                r = srv.wait(t)
+                assert r.status == lj.LJ_OK
+                lat.append((r.done_ns - r.submit_ns) * 1e-6)
+                free.put(b)
+
+        th = threading.Thread(target=collector)
+        th.start()
+        start = time.perf_counter()
+        next_t = start
+        for i, a, m in reqs:
+            if rate:
+                next_t += rng.exponential(1.0 / rate)
+                d = next_t - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+            b = free.get()
+            t = srv.submit(i, s_np[i, a:a + m], o_np[b, :m])
+            tickets.put((t, b, m))
+        th.join()
+        wall = time.perf_counter() - start
+        st = srv.stats
+        srv.close()
+        return wall, np.array(lat), st
+
+    plain = lj.lj_server_default_config(24 << 30)
+    plain.slots, plain.max_batch_requests = 1, 1
+    served = lj.lj_server_default_config(24 << 30)
+
+    sat_reqs = make_requests(max(200, nreq // 4))
+    keys_sat = sum(m for _, _, m in sat_reqs)
+    w_plain, _, _ = run(plain, sat_reqs, None)
+    w_served, _, st_sat = run(served, sat_reqs, None)
+    sat_rate = len(sat_reqs) / w_plain
+    print(f"[bench] saturation: plain {sat_rate:.1f} req/s, served "
+          f"{len(sat_reqs) / w_served:.1f} req/s", file=sys.stderr, flush=True)
+    loads = {}
+    for load in (0.5, 0.8):
+        reqs = make_requests(nreq)
+        keys = sum(m for _, _, m in reqs)
+        row = {}
+        for name, cfg in (("plain_per_request", plain), ("served", served)):
+            wall, lat, st = run(cfg, reqs, load * sat_rate)
+            row[name] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+                         "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                         "probes_per_s": keys / wall, "batches": int(st.batches),
+                         "max_batch": int(st.max_batch_size)}
+            print(f"[bench] load {load} {name}: {row[name]}", file=sys.stderr, flush=True)
+        loads[str(load)] = row
+    _json_line({
+        "metric": METRIC, "value": keys_sat / w_served, "unit": "probes/s",
+        "n_gpus": 1, "steps": len(sat_reqs), "warmup": 0,
+        "ms_per_step": round(w_served * 1e3 / len(sat_reqs), 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "serving-8x50M", "indexes": 8, "inner_keys_each": 50_000_000,
+                   "request_keys": "log-uniform 256..4194304", "requests_per_load": nreq},
+        "saturation": {"plain_per_request_probes_per_s": keys_sat / w_plain,
+                       "served_probes_per_s": keys_sat / w_served,
+                       "served_max_batch": int(st_sat.max_batch_size)},
+        "loads": loads,
+        "roofline": None, "cpu_baseline": None,
+    })
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +306,8 @@ def main():
     ap.add_argument("--leaf", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--cpu-sample", type=int, default=120_000_000,
                     help="outer keys in the timed oracle sample (0 = skip)")
+    ap.add_argument("--requests", type=int, default=1000,
+                    help="requests per load level in the serving workload")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the steps, run a plain device copy of this many MiB "
                          "(reference point for HBM byte counters)")
@@ -120,6 +317,11 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
+
+    if args.workload == "multi-index-64":
+        return bench_multi_index(args)
+    if args.workload == "serving-8x50M":
+        return bench_serving(args)
 
     import torch
     from paper_2111_08824_amd import lj

@@ -16,5 +16,5 @@ from .gen import (  # noqa: F401
 )
 from .configs import (  # noqa: F401
     Workload, c1_uniform, c2_lognormal_zipf, c3_dup_runs, multi_index_batches,
-    default_leaves,
+    default_leaves, resident_indexes,
 )

@@ -108,3 +108,28 @@ def multi_index_batches(k: int = 64, seed: int = 42, n_lo: float = 1e4,
                             R, S, default_leaves(n), int(round(m * 0.5)),
                             {"n": n, "m": m, "shape": shape}))
     return out
+
+
+def resident_indexes(k: int = 8, n: int = 50_000_000, pool: int = 8_000_000, seed: int = 42):
+    """k inner relations of n keys for the serving workload (3 uniform in
+    [0, 2^40), 3 lognormal(0, 2) scaled to 2^63, 2 seq_h, in that rotation),
+    each with a pool of outer keys (50% hits) that requests slice."""
+    shapes = ["uniform", "uniform", "uniform", "lognormal", "lognormal", "lognormal",
+              "seq_h", "seq_h"]
+    out = []
+    for i in range(k):
+        shape = shapes[i % len(shapes)]
+        s = seed * 7919 + i
+        if shape == "uniform":
+            R = gen.uniform_unique(n, 40, s)
+            hi = 2**40
+        elif shape == "lognormal":
+            R = gen.lognormal_unique(n, 2.0, s)
+            hi = 2**63
+        else:
+            R = gen.seq_holes(n, s)
+            hi = int(R[-1]) + int(R[-1]) // 8 + 2
+        S = gen.probe_mix(R, pool, 0.5, s + 1, miss_lo=0, miss_hi=hi)
+        out.append(Workload(f"resident{i}-{shape}-{n}", R, S, default_leaves(n), None,
+                            {"n": n, "shape": shape}))
+    return out
