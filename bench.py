@@ -184,7 +184,8 @@ def bench_serving(args) -> None:
     256..4M keys (log-uniform) at 0.5x and 0.8x the saturation rate of the
     plain per-request probe, run through the serving loop configured as the
     plain per-request probe (one stream, one request per launch) and as the
-    continuously batching server (4 streams, up to 64 requests per batch)."""
+    continuously batching server (8 streams, up to 16 requests and 2^22 keys
+    per batch)."""
     import threading
     import queue as pyqueue
 
@@ -262,7 +263,10 @@ def bench_serving(args) -> None:
     plain.slots, plain.max_batch_requests = 1, 1
     served = lj.lj_server_default_config(24 << 30)
 
-    sat_reqs = make_requests(max(200, nreq // 4))
+    warm = make_requests(64)
+    run(plain, warm, None)
+    run(served, warm, None)
+    sat_reqs = make_requests(nreq)
     keys_sat = sum(m for _, _, m in sat_reqs)
     w_plain, _, _ = run(plain, sat_reqs, None)
     w_served, _, st_sat = run(served, sat_reqs, None)

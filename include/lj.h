@@ -226,10 +226,12 @@ int lj_batch_autotune(const lj_batch_desc* descs, uint32_t k, hipStream_t stream
  * requests in arrival order while the head request's device footprint
  * (keys + output + workspace) fits the memory budget left, forms a batch as
  * soon as one of `slots` streams is free (so requests that arrive while
- * others run join the next batch), and enqueues the batch's copies and
- * fused probes on that stream; batches on different streams overlap on the
- * device.  A completion thread per stream copies results back, frees the
- * memory and wakes the waiters.  Device memory for requests comes from one
+ * others run join the next batch), and enqueues, request after request,
+ * the key copy, the fused probe and the count copy on that stream; batches
+ * on different streams overlap on the device and on the copy engines.  A
+ * completion thread per stream returns each request as soon as its own
+ * work is done (pairs copied back on a second stream), frees its memory and
+ * wakes its waiter.  Device memory for requests comes from one
  * arena of `budget_bytes` allocated at creation.
  */
 typedef struct {
@@ -261,7 +263,7 @@ typedef struct {
     uint64_t keys_probed;
 } lj_server_stats;
 
-/* Fill *config with defaults for a budget: 4 slots, 64 requests and 2^24
+/* Fill *config with defaults for a budget: 8 slots, 16 requests and 2^22
  * keys per batch, keys per lane 4/8/16/24. */
 void lj_server_default_config(lj_server_config* config, uint64_t budget_bytes);
 

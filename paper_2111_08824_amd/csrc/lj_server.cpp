@@ -81,9 +81,10 @@ struct Request {
 };
 
 struct Slot {
-    hipStream_t stream = nullptr;
-    hipEvent_t event = nullptr;
-    uint64_t* counts_host = nullptr;  // pinned, one per request of a batch
+    hipStream_t stream = nullptr;      // copies in, probes, counts out
+    hipStream_t ret_stream = nullptr;  // pairs back to the host
+    std::vector<hipEvent_t> events;    // one per request of a batch
+    uint64_t* counts_host = nullptr;   // pinned, one per request of a batch
     std::vector<Request*> batch;
     bool busy = false;
     bool has_work = false;
@@ -141,17 +142,17 @@ uint64_t footprint(const lj_index* idx, uint64_t m, uint64_t cap, Request* r) {
 
 }  // namespace
 
+// Per request, in batch order: keys in, fused probe, count out, then an
+// event, so that the completion thread can return each request as soon as
+// its own work is done.
 hipError_t lj_server::enqueue_batch(Slot* s) {
     hipError_t e = hipSuccess;
-    for (Request* r : s->batch) {
+    for (size_t i = 0; i < s->batch.size() && e == hipSuccess; ++i) {
+        Request* r = s->batch[i];
         char* base = arena_base + r->off;
         if (r->m)
             e = hipMemcpyAsync(base + r->s_off, r->s_host, 8 * r->m, hipMemcpyHostToDevice,
                                s->stream);
-        if (e != hipSuccess) return e;
-    }
-    for (Request* r : s->batch) {
-        char* base = arena_base + r->off;
         lj_batch_desc d;
         d.index = indexes[r->index_id];
         d.s_keys_dev = (const uint64_t*)(base + r->s_off);
@@ -159,17 +160,15 @@ hipError_t lj_server::enqueue_batch(Slot* s) {
         d.out_pairs_dev = r->devcap ? (lj_pair*)(base + r->out_off) : nullptr;
         d.out_capacity = r->devcap;
         d.out_count_dev = (uint64_t*)(base + r->cnt_off);
-        e = lj::enqueue_one(d, base + r->ws_off, cfg.keys_per_lane[lj::size_class(r->m)],
-                            s->stream);
-        if (e != hipSuccess) return e;
+        if (e == hipSuccess)
+            e = lj::enqueue_one(d, base + r->ws_off, cfg.keys_per_lane[lj::size_class(r->m)],
+                                s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&s->counts_host[i], base + r->cnt_off, 8, hipMemcpyDeviceToHost,
+                               s->stream);
+        if (e == hipSuccess) e = hipEventRecord(s->events[i], s->stream);
     }
-    for (size_t i = 0; i < s->batch.size(); ++i) {
-        Request* r = s->batch[i];
-        e = hipMemcpyAsync(&s->counts_host[i], arena_base + r->off + r->cnt_off, 8,
-                           hipMemcpyDeviceToHost, s->stream);
-        if (e != hipSuccess) return e;
-    }
-    return hipEventRecord(s->event, s->stream);
+    return e;
 }
 
 void lj_server::schedule_loop() {
@@ -232,38 +231,40 @@ void lj_server::slot_loop(Slot* s) {
         if (!s->has_work) break;
         std::vector<Request*> batch = s->batch;
         lk.unlock();
-        bool ok = hipEventSynchronize(s->event) == hipSuccess;
-        std::vector<uint64_t> counts(batch.size(), ~0ull);
-        for (size_t i = 0; i < batch.size() && ok; ++i) {
-            Request* r = batch[i];
-            counts[i] = s->counts_host[i];
-            if (r->res.status != LJ_OK || counts[i] == ~0ull) continue;
-            uint64_t n = std::min(counts[i], std::min(r->cap, r->devcap));
-            if (n)
-                ok = hipMemcpyAsync(r->out_host, arena_base + r->off + r->out_off,
-                                    n * sizeof(lj_pair), hipMemcpyDeviceToHost,
-                                    s->stream) == hipSuccess;
-        }
-        ok = ok && hipStreamSynchronize(s->stream) == hipSuccess;
-        const uint64_t t = now_ns();
-        lk.lock();
+        // Return requests one by one, as their own work finishes.
         for (size_t i = 0; i < batch.size(); ++i) {
             Request* r = batch[i];
-            if (r->res.status == LJ_OK) {
-                if (!ok || counts[i] == ~0ull) r->res.status = LJ_ERR_DEVICE;
-                else if (counts[i] > r->cap) r->res.status = LJ_ERR_CAPACITY;
+            bool ok = r->res.status == LJ_OK && hipEventSynchronize(s->events[i]) == hipSuccess;
+            uint64_t count = ok ? s->counts_host[i] : ~0ull;
+            if (ok && count != ~0ull) {
+                uint64_t n = std::min(count, std::min(r->cap, r->devcap));
+                if (n)
+                    ok = hipMemcpyAsync(r->out_host, arena_base + r->off + r->out_off,
+                                        n * sizeof(lj_pair), hipMemcpyDeviceToHost,
+                                        s->ret_stream) == hipSuccess &&
+                         hipStreamSynchronize(s->ret_stream) == hipSuccess;
             }
-            r->res.count = counts[i];
+            const uint64_t t = now_ns();
+            lk.lock();
+            if (r->res.status == LJ_OK) {
+                if (!ok || count == ~0ull) r->res.status = LJ_ERR_DEVICE;
+                else if (count > r->cap) r->res.status = LJ_ERR_CAPACITY;
+            }
+            r->res.count = count;
             r->res.done_ns = t;
             r->done = true;
             arena->release(r->off, r->bytes);
             stats.requests_done++;
             stats.keys_probed += r->m;
+            cv_done.notify_all();
+            cv_sched.notify_all();
+            lk.unlock();
         }
+        (void)hipStreamSynchronize(s->stream);
+        lk.lock();
         s->batch.clear();
         s->has_work = false;
         s->busy = false;
-        cv_done.notify_all();
         cv_sched.notify_all();
     }
 }
@@ -273,9 +274,9 @@ extern "C" {
 void lj_server_default_config(lj_server_config* c, uint64_t budget_bytes) {
     if (!c) return;
     c->budget_bytes = budget_bytes;
-    c->slots = 4;
-    c->max_batch_requests = 64;
-    c->max_batch_keys = 1ull << 24;
+    c->slots = 8;
+    c->max_batch_requests = 16;
+    c->max_batch_keys = 1ull << 22;
     c->keys_per_lane[0] = 4;
     c->keys_per_lane[1] = 8;
     c->keys_per_lane[2] = 16;
@@ -317,10 +318,19 @@ int lj_server_create(lj_index* const* indexes, uint32_t n, const lj_server_confi
         }
         sv->slots.push_back(s);
         if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&s->event, hipEventDisableTiming) != hipSuccess ||
+            hipStreamCreateWithFlags(&s->ret_stream, hipStreamNonBlocking) != hipSuccess ||
             hipHostMalloc((void**)&s->counts_host, 8ull * cfg->max_batch_requests) !=
-                hipSuccess)
+                hipSuccess) {
             st = LJ_ERR_DEVICE;
+            break;
+        }
+        for (uint32_t q = 0; q < cfg->max_batch_requests && st == LJ_OK; ++q) {
+            hipEvent_t ev = nullptr;
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+                st = LJ_ERR_DEVICE;
+            else
+                s->events.push_back(ev);
+        }
     }
     if (st != LJ_OK) {
         lj_server_destroy(sv);
@@ -407,7 +417,8 @@ void lj_server_destroy(lj_server* sv) {
     for (Slot* s : sv->slots) {
         if (s->worker.joinable()) s->worker.join();
         if (s->stream) (void)hipStreamDestroy(s->stream);
-        if (s->event) (void)hipEventDestroy(s->event);
+        if (s->ret_stream) (void)hipStreamDestroy(s->ret_stream);
+        for (hipEvent_t ev : s->events) (void)hipEventDestroy(ev);
         if (s->counts_host) (void)hipHostFree(s->counts_host);
         delete s;
     }
