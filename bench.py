@@ -308,6 +308,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lognormal-zipf-200M")
     ap.add_argument("--leaf", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--search", choices=["binary", "exponential"], default="binary",
+                    help="last-mile search inside the error bounds")
     ap.add_argument("--cpu-sample", type=int, default=120_000_000,
                     help="outer keys in the timed oracle sample (0 = skip)")
     ap.add_argument("--requests", type=int, default=1000,
@@ -335,6 +337,8 @@ def main():
     print(f"[bench] workload {w.name}: n={len(w.R)} m={len(w.S)} leaves={w.leaves} "
           f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
     flags = lj.LJ_LEAF_FP32 if args.leaf == "fp32" else lj.LJ_LEAF_FP64
+    if args.search == "exponential":
+        flags |= lj.LJ_SEARCH_EXPONENTIAL
     stream = torch.cuda.current_stream()
     ix = lj.lj_build_rmi(w.R, w.leaves, flags, stream)
     st = ix.stats
@@ -404,7 +408,7 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": w.name, "n": len(w.R), "m": m, "leaves": w.leaves,
-                   "leaf_model": args.leaf, "pairs": int(count),
+                   "leaf_model": args.leaf, "search": args.search, "pairs": int(count),
                    "mean_window": round(st.mean_window, 2), "max_window": int(st.max_window)},
         "roofline": roof,
         "cpu_baseline": cpu,

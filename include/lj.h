@@ -55,10 +55,14 @@ enum {
     LJ_ERR_TIMEOUT = -8    /* a wait ended before the request completed */
 };
 
-/* Leaf-model arithmetic.  Exactly one must be given to lj_build_rmi. */
+/* Build flags.  Exactly one leaf arithmetic must be given to lj_build_rmi;
+ * the search flag is optional. */
 enum {
-    LJ_LEAF_FP32 = 1u, /* leaf model evaluated with fmaf on f32 parameters */
-    LJ_LEAF_FP64 = 2u  /* leaf model evaluated with fma on f64 parameters */
+    LJ_LEAF_FP32 = 1u,          /* leaf model evaluated with fmaf on f32 parameters */
+    LJ_LEAF_FP64 = 2u,          /* leaf model evaluated with fma on f64 parameters */
+    LJ_SEARCH_EXPONENTIAL = 4u  /* last-mile search gallops out from the prediction
+                                   (steps 8, 16, 32, ...) inside the error bounds, then
+                                   bisects; without it, binary search over the bounds */
 };
 
 /*
@@ -71,7 +75,9 @@ enum {
  *   n            number of keys, 0 <= n < 2^31.  n = 0 gives an index for
  *                which every probe finds nothing.
  *   leaves       number of leaf models, 1 <= leaves <= 2^26.
- *   flags        LJ_LEAF_FP32 or LJ_LEAF_FP64.
+ *   flags        LJ_LEAF_FP32 or LJ_LEAF_FP64, optionally with
+ *                LJ_SEARCH_EXPONENTIAL (the result is the same; only the
+ *                order in which the window is searched changes).
  *   stream       stream used for the uploads (the call returns after they
  *                complete).
  *   out_index    receives the new index; free it with lj_free_index.
@@ -306,7 +312,7 @@ void lj_server_destroy(lj_server* server);
 typedef struct {
     uint64_t n;               /* keys in R */
     uint32_t leaves;          /* leaf models */
-    uint32_t flags;           /* LJ_LEAF_FP32 or LJ_LEAF_FP64 */
+    uint32_t flags;           /* the build flags */
     uint32_t nonempty_leaves; /* leaves with at least one key */
     uint32_t max_leaf_keys;   /* keys in the largest leaf */
     uint64_t max_mult;        /* longest run of equal keys in R */

@@ -48,7 +48,8 @@ int check_device(const lj_index* idx) {
 int validate_build(const uint64_t* r, uint64_t n, uint32_t leaves, uint32_t flags) {
     if (n > 0 && !r) return LJ_ERR_ARG;
     if (leaves == 0) return LJ_ERR_ARG;
-    if (flags != LJ_LEAF_FP32 && flags != LJ_LEAF_FP64) return LJ_ERR_ARG;
+    if ((flags & ~7u) || ((flags & 3u) != LJ_LEAF_FP32 && (flags & 3u) != LJ_LEAF_FP64))
+        return LJ_ERR_ARG;
     if (n >= kMaxN || leaves > kMaxLeaves) return LJ_ERR_TOO_LARGE;
     for (uint64_t i = 1; i < n; ++i)
         if (r[i - 1] > r[i]) return LJ_ERR_UNSORTED;
@@ -98,9 +99,9 @@ int lj_build_rmi(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves, uint3
         return LJ_ERR_DEVICE;
     }
     const uint64_t rbytes = (n ? n : 1) * sizeof(uint64_t);
-    const void* lsrc = flags == LJ_LEAF_FP32 ? (const void*)idx->leaf32.data()
+    const void* lsrc = lj::leaf_fp32(flags) ? (const void*)idx->leaf32.data()
                                              : (const void*)idx->leaf64.data();
-    const uint64_t lbytes = (uint64_t)leaves * (flags == LJ_LEAF_FP32 ? sizeof(lj::LeafF32)
+    const uint64_t lbytes = (uint64_t)leaves * (lj::leaf_fp32(flags) ? sizeof(lj::LeafF32)
                                                                       : sizeof(lj::LeafF64));
     if (hipMalloc((void**)&idx->r_dev, rbytes) != hipSuccess ||
         hipMalloc(&idx->leaf_dev, lbytes) != hipSuccess) {
@@ -261,7 +262,7 @@ int lj_predict_windows_host(const lj_index* idx, const uint64_t* keys, uint64_t 
         int64_t lo = 1, hi = 0, pr = -1;
         uint32_t cnt = 0, pos0 = 0;
         int32_t elo = 0, ehi = 0, rel = 0;
-        if (idx->flags == LJ_LEAF_FP32) {
+        if (lj::leaf_fp32(idx->flags)) {
             const lj::LeafF32& lf = idx->leaf32[l];
             cnt = lf.cnt;
             if (cnt) rel = lj::predict_rel(lf, x);

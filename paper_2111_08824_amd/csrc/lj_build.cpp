@@ -179,7 +179,7 @@ int fit_rmi(const uint64_t* r, uint64_t n, uint32_t L, uint32_t flags, lj_index*
     }
     idx->max_mult = mm;
 
-    if (flags == LJ_LEAF_FP32) {
+    if (leaf_fp32(flags)) {
         fit_leaves(r, pos0, cnt, L, idx->leaf32);
         leaf_stats(idx->leaf32, idx);
     } else {

@@ -34,6 +34,8 @@ struct lj_index {
 
 namespace lj {
 
+inline bool leaf_fp32(uint32_t flags) { return (flags & 3u) == LJ_LEAF_FP32; }
+
 // Fit the root and leaf models and their error bounds on the host (no HIP
 // calls).  Returns an LJ_* status.
 int fit_rmi(const uint64_t* r, uint64_t n, uint32_t leaves, uint32_t flags,
@@ -83,9 +85,11 @@ struct TileJob {
 };
 constexpr uint32_t kJobFp64 = 1u;
 constexpr uint32_t kJobDup = 2u;
+constexpr uint32_t kJobExp = 4u;
 
 inline uint32_t job_kind(const lj_index* idx) {
-    return (idx->flags == LJ_LEAF_FP64 ? kJobFp64 : 0u) | (idx->max_mult > 1 ? kJobDup : 0u);
+    return ((idx->flags & LJ_LEAF_FP64) ? kJobFp64 : 0u) | (idx->max_mult > 1 ? kJobDup : 0u) |
+           ((idx->flags & LJ_SEARCH_EXPONENTIAL) ? kJobExp : 0u);
 }
 
 // Kernel launchers (lj_kernels.hip).  Return hipSuccess or the launch error.

@@ -163,7 +163,7 @@ __device__ void finish_tile(const TileJob& j) {
 // Probe one tile of a batch: kBlock threads, the first `kpl` (<= kItems) keys
 // of each lane are live; key k of thread t is outer key
 // tile*kBlock*kpl + k*kBlock + t.
-template <class Leaf, bool kUnique, int kItems, bool kWithOffsets>
+template <class Leaf, bool kUnique, int kItems, bool kWithOffsets, bool kExp>
 __device__ void probe_tile(const TileJob& j, const uint32_t tile, const uint32_t kpl,
                            TileShared<kItems, kWithOffsets>& sh) {
     static_assert(kUnique || kWithOffsets, "the duplicate path needs LDS offsets");
@@ -174,7 +174,9 @@ __device__ void probe_tile(const TileJob& j, const uint32_t tile, const uint32_t
     const Leaf* leaves = (const Leaf*)j.leaves;
     const uint64_t* __restrict__ R = j.r;
     uint64_t x[kItems];
-    uint32_t first[kItems], len[kItems];
+    uint32_t first[kItems], len[kItems];  // binary search: window start, length
+    int32_t lo[kExp ? kItems : 1], hi[kExp ? kItems : 1];  // exponential search:
+    uint32_t pos[kExp ? kItems : 1], stp[kExp ? kItems : 1];  // bracket, probe, step|phase
     uint32_t end[kUnique ? 1 : kItems];
     uint32_t eqmask = 0;  // bit k: the last R[mid] >= x[k] read equals x[k]
     static_assert(kItems <= 32, "eqmask holds one bit per key");
@@ -204,33 +206,98 @@ __device__ void probe_tile(const TileJob& j, const uint32_t tile, const uint32_t
             if (wlo < 0) wlo = 0;
             if (whi > (int64_t)lf[u].cnt - 1) whi = (int64_t)lf[u].cnt - 1;
             const bool live = ((validmask >> k) & 1u) && lf[u].cnt != 0 && wlo <= whi;
-            first[k] = live ? lf[u].pos0 + (uint32_t)wlo : 0;
-            len[k] = live ? (uint32_t)(whi - wlo + 1) : 0;
+            if constexpr (kExp) {
+                // Open bracket (lo, hi) around the window; the first probe is
+                // the prediction itself, clamped into the window.
+                const int32_t a = (int32_t)lf[u].pos0 + (int32_t)wlo;
+                const int32_t b = (int32_t)lf[u].pos0 + (int32_t)whi;
+                int32_t pr = (int32_t)lf[u].pos0 + (int32_t)rel;
+                pr = pr < a ? a : (pr > b ? b : pr);
+                lo[k] = live ? a - 1 : 0;
+                hi[k] = live ? b + 1 : 0;
+                pos[k] = live ? (uint32_t)pr : 0;
+                stp[k] = 0;  // phase 0: probe the prediction
+            } else {
+                first[k] = live ? lf[u].pos0 + (uint32_t)wlo : 0;
+                len[k] = live ? (uint32_t)(whi - wlo + 1) : 0;
+            }
             if constexpr (!kUnique) end[k] = live ? lf[u].pos0 + (uint32_t)whi + 1 : 0;
         }
     }
 
-    // 3: lockstep lower_bound over the windows.  Finished keys re-read R[0]
-    // (a cached line) so that the loop body has no branches and the loads of
-    // all keys of the lane issue back to back.  When the loop ends, first[k]
-    // is the window end or the position of the last element read with
-    // R[mid] >= x[k], so bit k of eqmask tells whether x[k] was found.
-    for (;;) {
-        uint32_t anylen = 0;
+    if constexpr (kExp) {
+        // 3': lockstep exponential search from the prediction, bounded by the
+        // window.  The bracket (lo, hi) always satisfies R[lo] < x <= R[hi]
+        // (positions a-1 and b+1 standing for the window's edges).  Phase 0
+        // reads the prediction; phase 1 (2) gallops right (left) with steps
+        // 8, 16, 32, ...; phase 3 bisects the bracket.  A key is done when
+        // hi - lo <= 1; hi is then the lower bound and the last probe that
+        // set hi tells whether x was found.
+        for (;;) {
+            bool any = false;
 #pragma unroll
-        for (int k = 0; k < kItems; ++k) anylen |= len[k];
-        if (!anylen) break;
-        uint64_t v[kItems];
+            for (int k = 0; k < kItems; ++k) any |= hi[k] - lo[k] > 1;
+            if (!any) break;
+            uint64_t v[kItems];
 #pragma unroll
-        for (int k = 0; k < kItems; ++k) v[k] = R[len[k] ? first[k] + (len[k] >> 1) : 0];
+            for (int k = 0; k < kItems; ++k) v[k] = R[hi[k] - lo[k] > 1 ? pos[k] : 0];
 #pragma unroll
-        for (int k = 0; k < kItems; ++k) {
-            const uint32_t half = len[k] >> 1;
-            const bool act = len[k] != 0;
-            const bool lt = v[k] < x[k];
-            first[k] = (act && lt) ? first[k] + half + 1 : first[k];
-            if (act && !lt) eqmask = (eqmask & ~(1u << k)) | ((v[k] == x[k] ? 1u : 0u) << k);
-            len[k] = act ? (lt ? len[k] - half - 1 : half) : 0;
+            for (int k = 0; k < kItems; ++k) {
+                if (hi[k] - lo[k] <= 1) continue;
+                const uint32_t phase = stp[k] & 7u;
+                uint32_t lg = stp[k] >> 3;  // step = 2^lg
+                const bool lt = v[k] < x[k];
+                if (lt) lo[k] = (int32_t)pos[k];
+                else {
+                    hi[k] = (int32_t)pos[k];
+                    eqmask = (eqmask & ~(1u << k)) | ((v[k] == x[k] ? 1u : 0u) << k);
+                }
+                uint32_t nphase = phase;
+                if (phase == 0) {
+                    nphase = lt ? 1u : 2u;
+                    lg = 3;
+                } else if (phase == 1) {
+                    if (lt) lg = lg < 30 ? lg + 1 : 30;
+                    else nphase = 3;
+                } else if (phase == 2) {
+                    if (!lt) lg = lg < 30 ? lg + 1 : 30;
+                    else nphase = 3;
+                }
+                stp[k] = (lg << 3) | nphase;
+                const uint32_t step = 1u << lg;
+                const int32_t l = lo[k], h = hi[k];
+                int32_t np;
+                if (nphase == 1) np = (int64_t)l + step < h - 1 ? l + (int32_t)step : h - 1;
+                else if (nphase == 2) np = (int64_t)h - step > l + 1 ? h - (int32_t)step : l + 1;
+                else np = l + ((h - l) >> 1);
+                pos[k] = (uint32_t)np;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) first[k] = (uint32_t)hi[k];
+    } else {
+        // 3: lockstep lower_bound over the windows.  Finished keys re-read R[0]
+        // (a cached line) so that the loop body has no branches and the loads of
+        // all keys of the lane issue back to back.  When the loop ends, first[k]
+        // is the window end or the position of the last element read with
+        // R[mid] >= x[k], so bit k of eqmask tells whether x[k] was found.
+        for (;;) {
+            uint32_t anylen = 0;
+    #pragma unroll
+            for (int k = 0; k < kItems; ++k) anylen |= len[k];
+            if (!anylen) break;
+            uint64_t v[kItems];
+    #pragma unroll
+            for (int k = 0; k < kItems; ++k) v[k] = R[len[k] ? first[k] + (len[k] >> 1) : 0];
+    #pragma unroll
+            for (int k = 0; k < kItems; ++k) {
+                const uint32_t half = len[k] >> 1;
+                const bool act = len[k] != 0;
+                const bool lt = v[k] < x[k];
+                first[k] = (act && lt) ? first[k] + half + 1 : first[k];
+                if (act && !lt) eqmask = (eqmask & ~(1u << k)) | ((v[k] == x[k] ? 1u : 0u) << k);
+                len[k] = act ? (lt ? len[k] - half - 1 : half) : 0;
+            }
         }
     }
 
@@ -377,13 +444,13 @@ __device__ void probe_tile(const TileJob& j, const uint32_t tile, const uint32_t
     finish_tile(j);
 }
 
-template <class Leaf, bool kUnique, int kItems>
+template <class Leaf, bool kUnique, int kItems, bool kExp>
 __global__ __launch_bounds__(kBlock) void probe_join_kernel(TileJob j, uint32_t* tile_counter) {
     __shared__ uint32_t s_tile;
     __shared__ TileShared<kItems, !kUnique> sh;
     if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
     __syncthreads();
-    probe_tile<Leaf, kUnique, kItems, !kUnique>(j, s_tile, kItems, sh);
+    probe_tile<Leaf, kUnique, kItems, !kUnique, kExp>(j, s_tile, kItems, sh);
 }
 
 __global__ void zero_words(uint64_t* w, uint64_t nwords) {
@@ -460,27 +527,27 @@ hipError_t launch_zero_words(uint64_t* p, uint64_t nwords, hipStream_t stream) {
 
 namespace {
 
-template <int kItems>
+template <int kItems, bool kExp>
 hipError_t launch_probe_items(const TileJob& j, uint32_t* ctr, hipStream_t stream) {
     dim3 grid(j.ntiles), block(kBlock);
-    switch (j.kind) {
+    switch (j.kind & (kJobFp64 | kJobDup)) {
         case 0:
-            hipLaunchKernelGGL((probe_join_kernel<LeafF32, true, kItems>), grid, block, 0, stream,
-                               j, ctr);
+            hipLaunchKernelGGL((probe_join_kernel<LeafF32, true, kItems, kExp>), grid, block, 0,
+                               stream, j, ctr);
             break;
         case kJobDup:
             if constexpr (kItems <= kItemsDup)
-                hipLaunchKernelGGL((probe_join_kernel<LeafF32, false, kItems>), grid, block, 0,
-                                   stream, j, ctr);
+                hipLaunchKernelGGL((probe_join_kernel<LeafF32, false, kItems, kExp>), grid, block,
+                                   0, stream, j, ctr);
             break;
         case kJobFp64:
-            hipLaunchKernelGGL((probe_join_kernel<LeafF64, true, kItems>), grid, block, 0, stream,
-                               j, ctr);
+            hipLaunchKernelGGL((probe_join_kernel<LeafF64, true, kItems, kExp>), grid, block, 0,
+                               stream, j, ctr);
             break;
         default:
             if constexpr (kItems <= kItemsDup)
-                hipLaunchKernelGGL((probe_join_kernel<LeafF64, false, kItems>), grid, block, 0,
-                                   stream, j, ctr);
+                hipLaunchKernelGGL((probe_join_kernel<LeafF64, false, kItems, kExp>), grid, block,
+                                   0, stream, j, ctr);
             break;
     }
     return hipGetLastError();
@@ -525,11 +592,16 @@ hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m, lj_p
         if (e != hipSuccess) return e;
     }
     uint32_t* ctr = &hdr->tile_counter;
+    const bool ex = (kind & kJobExp) != 0;
     switch (kpl) {
-        case 4: e = launch_probe_items<4>(j, ctr, stream); break;
-        case 8: e = launch_probe_items<8>(j, ctr, stream); break;
-        case 16: e = launch_probe_items<16>(j, ctr, stream); break;
-        default: e = launch_probe_items<24>(j, ctr, stream); break;
+        case 4: e = ex ? launch_probe_items<4, true>(j, ctr, stream)
+                       : launch_probe_items<4, false>(j, ctr, stream); break;
+        case 8: e = ex ? launch_probe_items<8, true>(j, ctr, stream)
+                       : launch_probe_items<8, false>(j, ctr, stream); break;
+        case 16: e = ex ? launch_probe_items<16, true>(j, ctr, stream)
+                        : launch_probe_items<16, false>(j, ctr, stream); break;
+        default: e = ex ? launch_probe_items<24, true>(j, ctr, stream)
+                        : launch_probe_items<24, false>(j, ctr, stream); break;
     }
     if (e != hipSuccess) return e;
     if (ev1) e = hipEventRecord(ev1, stream);
@@ -540,7 +612,7 @@ hipError_t launch_self_check(const lj_index* idx, uint64_t* viol, hipStream_t st
     hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, stream, viol, (uint64_t)1);
     unsigned g = grid_for(idx->n, 256);
     if (idx->n == 0) return hipGetLastError();
-    if (idx->flags == LJ_LEAF_FP32)
+    if (leaf_fp32(idx->flags))
         hipLaunchKernelGGL(self_check_kernel<LeafF32>, dim3(g), dim3(256), 0, stream,
                            idx->r_dev, idx->n, (const LeafF32*)idx->leaf_dev, idx->root,
                            (unsigned long long*)viol);
@@ -556,7 +628,7 @@ hipError_t launch_predict_windows(const lj_index* idx, const uint64_t* keys, uin
                                   hipStream_t stream) {
     if (m == 0) return hipSuccess;
     unsigned g = grid_for(m, 256);
-    if (idx->flags == LJ_LEAF_FP32)
+    if (leaf_fp32(idx->flags))
         hipLaunchKernelGGL(predict_windows_kernel<LeafF32>, dim3(g), dim3(256), 0, stream,
                            keys, m, (const LeafF32*)idx->leaf_dev, idx->root, leaf, pred, wlo,
                            whi);

@@ -29,6 +29,7 @@ LJ_ERR_TIMEOUT = -8
 
 LJ_LEAF_FP32 = 1
 LJ_LEAF_FP64 = 2
+LJ_SEARCH_EXPONENTIAL = 4
 
 EXPORTED = (
     "lj_build_rmi", "lj_free_index", "lj_probe_join", "lj_probe_workspace_bytes",

@@ -16,6 +16,8 @@ pytestmark = pytest.mark.gpu
 
 U64MAX = 2**64 - 1
 FLAGS = [lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP64]
+EXP = lj.LJ_SEARCH_EXPONENTIAL
+ALL_FLAGS = FLAGS + [lj.LJ_LEAF_FP32 | EXP, lj.LJ_LEAF_FP64 | EXP]
 
 
 def gpu_join(R, S, leaves, flags, capacity=None):
@@ -36,38 +38,40 @@ def assert_parity(R, S, leaves, flags, label=""):
     return got
 
 
-@pytest.mark.parametrize("flags", FLAGS)
+@pytest.mark.parametrize("flags", ALL_FLAGS)
 def test_uniform_1m(flags):
     w = workloads.c1_uniform()
     got = assert_parity(w.R, w.S, w.leaves, flags, w.name)
     assert len(got) == w.expected_count == 500_000
 
 
-@pytest.mark.parametrize("flags", FLAGS)
+@pytest.mark.parametrize("flags", ALL_FLAGS)
 def test_lognormal_zipf_2m(flags):
     w = workloads.c2_lognormal_zipf(scale=0.01)
     got = assert_parity(w.R, w.S, w.leaves, flags, w.name)
     assert len(got) == w.expected_count
 
 
-@pytest.mark.parametrize("flags", FLAGS)
+@pytest.mark.parametrize("flags", ALL_FLAGS)
 def test_dup_runs_1m(flags):
     w = workloads.c3_dup_runs(scale=0.01)
     assert_parity(w.R, w.S, w.leaves, flags, w.name)
 
 
 @pytest.mark.parametrize("m", [1, 2, 63, 64, 255, 1023, 1024, 1025, 4096 + 7, 77_777])
-def test_ragged_tile_tails(m):
+@pytest.mark.parametrize("search", [0, EXP])
+def test_ragged_tile_tails(m, search):
     R = workloads.gen.uniform_unique(50_000, 20, 3)
     S = workloads.gen.probe_mix(R, m, 0.6, 4, miss_hi=2**20)
-    assert_parity(R, S, 256, lj.LJ_LEAF_FP32, f"tail m={m}")
+    assert_parity(R, S, 256, lj.LJ_LEAF_FP32 | search, f"tail m={m}")
 
 
 @pytest.mark.parametrize("leaves", [1, 2, 1000, 200_003])
-def test_leaf_counts(leaves):
+@pytest.mark.parametrize("search", [0, EXP])
+def test_leaf_counts(leaves, search):
     R = workloads.gen.lognormal_unique(50_000, 2.0, 5)
     S = workloads.gen.probe_mix(R, 60_000, 0.5, 6, miss_hi=2**63)
-    assert_parity(R, S, leaves, lj.LJ_LEAF_FP32, f"leaves={leaves}")
+    assert_parity(R, S, leaves, lj.LJ_LEAF_FP32 | search, f"leaves={leaves}")
 
 
 def test_heavy_duplicates_load_balanced_emission():
@@ -77,6 +81,8 @@ def test_heavy_duplicates_load_balanced_emission():
                         np.arange(2000, 2100, dtype=np.uint64)])
     S = np.array([1000, 5, 1000, 7000, 2050, 1000], dtype=np.uint64)
     got = assert_parity(R, S, 8, lj.LJ_LEAF_FP32, "heavy duplicates")
+    assert len(got) == 3 * 5000 + 2
+    got = assert_parity(R, S, 8, lj.LJ_LEAF_FP32 | EXP, "heavy duplicates, exponential")
     assert len(got) == 3 * 5000 + 2
 
 
@@ -90,7 +96,7 @@ def test_all_equal_inner_relation():
 def test_extreme_keys():
     R = np.array([0, 0, 1, 2**63, U64MAX - 1, U64MAX, U64MAX], dtype=np.uint64)
     S = np.array([U64MAX, 0, 7, 2**63, U64MAX - 2, 1, U64MAX], dtype=np.uint64)
-    for flags in FLAGS:
+    for flags in ALL_FLAGS:
         assert_parity(R, S, 3, flags, "extreme keys")
 
 

@@ -55,6 +55,9 @@ def test_argument_errors():
     assert _build_status(R, leaves=0) == lj.LJ_ERR_ARG
     assert _build_status(R, flags=0) == lj.LJ_ERR_ARG
     assert _build_status(R, flags=3) == lj.LJ_ERR_ARG
+    assert _build_status(R, flags=lj.LJ_SEARCH_EXPONENTIAL) == lj.LJ_ERR_ARG
+    assert _build_status(R, flags=lj.LJ_LEAF_FP64 | lj.LJ_SEARCH_EXPONENTIAL) == lj.LJ_OK
+    assert _build_status(R, flags=lj.LJ_LEAF_FP32 | 8) == lj.LJ_ERR_ARG
     assert _build_status(R, leaves=2**26 + 1) == lj.LJ_ERR_TOO_LARGE
     assert _build_status(R, n=2**31) == lj.LJ_ERR_TOO_LARGE  # checked before reading R
     h = ctypes.c_void_p()
