@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "outer-key probes/sec + achieved HBM GB/s vs roofline; p50/p99 probe latency"
 HBM_PEAK_GBS = 8000.0
 PROBE_KERNEL_SOURCES = ["paper_2111_08824_amd/csrc/lj_kernels.hip",
+                        "paper_2111_08824_amd/csrc/lj_device.h",
                         "paper_2111_08824_amd/csrc/rmi_eval.h",
                         "paper_2111_08824_amd/csrc/lj_internal.h"]
 
@@ -42,10 +43,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str):
-    """HBM bytes per probe launch from the committed rocprofv3 counter summary,
-    or None when absent or taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", f"probe_{workload}_hbm_counters.md")
+def load_traffic(workload: str, binned: bool):
+    """HBM bytes per launch of the timed kernel from the committed rocprofv3
+    counter summary, or None when absent or taken on a different kernel
+    source."""
+    kind = "probe_binned" if binned else "probe"
+    path = os.path.join(ROOT, "profiles", f"{kind}_{workload}_hbm_counters.md")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -72,11 +75,14 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def algorithmic_bytes(pairs_dev, count: int, m: int) -> float:
-    """Compulsory HBM bytes of one probe launch: 8 B per outer key read, one
-    64 B sector of R per outer key (its insertion point, or every sector its
-    match run spans), and 8 B per emitted pair.  Computed from the emitted
-    pairs: a key with matches owns one contiguous run of r indices."""
+def algorithmic_bytes(pairs_dev, count: int, m: int, out_per_key: float = 0.0,
+                      out_per_pair: float = 8.0) -> float:
+    """Compulsory HBM bytes of one launch of the probe kernel: 8 B per outer
+    key read, one 64 B sector of R per outer key (its insertion point, or
+    every sector its match run spans), and its output: 8 B per emitted pair
+    (fused probe), or out_per_key bytes of per-key result (search kernel of
+    the binned probe).  Computed from the emitted pairs: a key with matches
+    owns one contiguous run of r indices."""
     import torch
     sectors = float(m)
     if count:
@@ -88,7 +94,7 @@ def algorithmic_bytes(pairs_dev, count: int, m: int) -> float:
         last[:-1] = new[1:]
         span = (r[last] // 8 - r[new] // 8 + 1).sum().item()
         sectors += float(span) - float(new.sum().item())
-    return 8.0 * m + 64.0 * sectors + 8.0 * count
+    return 8.0 * m + 64.0 * sectors + out_per_key * m + out_per_pair * count
 
 
 def cpu_baseline(w, sample: int):
@@ -310,6 +316,8 @@ def main():
     ap.add_argument("--leaf", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--search", choices=["binary", "exponential"], default="binary",
                     help="last-mile search inside the error bounds")
+    ap.add_argument("--probe", choices=["direct", "binned"], default="direct",
+                    help="probe S in its own order, or partitioned by key range first")
     ap.add_argument("--cpu-sample", type=int, default=120_000_000,
                     help="outer keys in the timed oracle sample (0 = skip)")
     ap.add_argument("--requests", type=int, default=1000,
@@ -339,6 +347,9 @@ def main():
     flags = lj.LJ_LEAF_FP32 if args.leaf == "fp32" else lj.LJ_LEAF_FP64
     if args.search == "exponential":
         flags |= lj.LJ_SEARCH_EXPONENTIAL
+    binned = args.probe == "binned"
+    if binned:
+        flags |= lj.LJ_PROBE_BINNED
     stream = torch.cuda.current_stream()
     ix = lj.lj_build_rmi(w.R, w.leaves, flags, stream)
     st = ix.stats
@@ -384,13 +395,17 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    alg = algorithmic_bytes(out, int(count), m)
+    if binned:  # search kernel: keys in, one 4-byte (8 with duplicates) result out
+        alg = algorithmic_bytes(out, int(count), m, 4.0 if st.max_mult <= 1 else 8.0, 0.0)
+    else:
+        alg = algorithmic_bytes(out, int(count), m)
     achieved = alg / (kern_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": load_traffic(w.name),
+            "traffic": load_traffic(w.name, binned),
             "algorithmic_bytes_per_launch": alg,
-            "kernel": "probe_join_kernel", "kernel_ms": round(kern_ms, 4)}
+            "kernel": "probe_binned_kernel" if binned else "probe_join_kernel",
+            "kernel_ms": round(kern_ms, 4)}
 
     cpu = cpu_baseline(w, min(args.cpu_sample, m)) if args.cpu_sample else None
     lat_ms = np.array(lat) * 1e3
@@ -408,7 +423,8 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": w.name, "n": len(w.R), "m": m, "leaves": w.leaves,
-                   "leaf_model": args.leaf, "search": args.search, "pairs": int(count),
+                   "leaf_model": args.leaf, "search": args.search, "probe": args.probe,
+                   "pairs": int(count),
                    "mean_window": round(st.mean_window, 2), "max_window": int(st.max_window)},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -51,7 +51,7 @@ enum {
     LJ_ERR_CAPACITY = -4,  /* more pairs than out_capacity (count still set) */
     LJ_ERR_DEVICE = -5,    /* a HIP call failed, or a kernel reported an error */
     LJ_ERR_OOM = -6,       /* device or host allocation failed */
-    LJ_ERR_WORKSPACE = -7, /* workspace smaller than lj_probe_workspace_bytes(m) */
+    LJ_ERR_WORKSPACE = -7, /* workspace smaller than lj_probe_workspace_bytes() */
     LJ_ERR_TIMEOUT = -8    /* a wait ended before the request completed */
 };
 
@@ -60,9 +60,15 @@ enum {
 enum {
     LJ_LEAF_FP32 = 1u,          /* leaf model evaluated with fmaf on f32 parameters */
     LJ_LEAF_FP64 = 2u,          /* leaf model evaluated with fma on f64 parameters */
-    LJ_SEARCH_EXPONENTIAL = 4u  /* last-mile search gallops out from the prediction
+    LJ_SEARCH_EXPONENTIAL = 4u, /* last-mile search gallops out from the prediction
                                    (steps 8, 16, 32, ...) inside the error bounds, then
                                    bisects; without it, binary search over the bounds */
+    LJ_PROBE_BINNED = 8u        /* probes put S in key order first: 4096 equi-depth key
+                                   ranges of R, two stable partition passes, searches
+                                   in that order with each XCD on its own ranges, results
+                                   put back in S order before emission (the locality of
+                                   buffering requests per node, Section III-B).  Same
+                                   output; about 28 more workspace bytes per outer key */
 };
 
 /*
@@ -76,8 +82,8 @@ enum {
  *                which every probe finds nothing.
  *   leaves       number of leaf models, 1 <= leaves <= 2^26.
  *   flags        LJ_LEAF_FP32 or LJ_LEAF_FP64, optionally with
- *                LJ_SEARCH_EXPONENTIAL (the result is the same; only the
- *                order in which the window is searched changes).
+ *                LJ_SEARCH_EXPONENTIAL and LJ_PROBE_BINNED (the result is
+ *                the same; only the order of the work changes).
  *   stream       stream used for the uploads (the call returns after they
  *                complete).
  *   out_index    receives the new index; free it with lj_free_index.
@@ -123,8 +129,9 @@ int lj_probe_join(const lj_index* index, const uint64_t* s_keys_dev, uint64_t m,
                   lj_pair* out_pairs_dev, uint64_t out_capacity,
                   uint64_t* out_count_host, hipStream_t stream);
 
-/* Bytes of device workspace lj_probe_join_async needs for m outer keys. */
-uint64_t lj_probe_workspace_bytes(uint64_t m);
+/* Bytes of device workspace lj_probe_join_async needs for m outer keys
+ * against `index` (0 for a NULL index). */
+uint64_t lj_probe_workspace_bytes(const lj_index* index, uint64_t m);
 
 /*
  * Asynchronous probe: same result as lj_probe_join, but nothing is read
@@ -134,7 +141,7 @@ uint64_t lj_probe_workspace_bytes(uint64_t m);
  *                   UINT64_MAX if a kernel hit its internal wait bound (a
  *                   device fault condition; the pairs are then invalid).
  *   workspace_dev   caller-owned device scratch of at least
- *                   lj_probe_workspace_bytes(m) bytes, 256-byte aligned;
+ *                   lj_probe_workspace_bytes(index, m) bytes, 256-byte aligned;
  *                   calls that share one workspace must be ordered on one
  *                   stream.
  *
@@ -369,7 +376,8 @@ int lj_build_rmi_host_only(const uint64_t* r_keys_host, uint64_t n,
 /*
  * Timing hook for benchmarks: the next lj_probe_join or lj_probe_join_async
  * call made by this host thread records `start` immediately before and
- * `stop` immediately after its probe kernel, on the call's stream.  Pass
+ * `stop` immediately after its probe kernel (with LJ_PROBE_BINNED: the
+ * search kernel over the partitioned keys), on the call's stream.  Pass
  * NULL events to disable.
  */
 int lj_probe_set_timing_events(hipEvent_t start, hipEvent_t stop);

@@ -48,7 +48,7 @@ int check_device(const lj_index* idx) {
 int validate_build(const uint64_t* r, uint64_t n, uint32_t leaves, uint32_t flags) {
     if (n > 0 && !r) return LJ_ERR_ARG;
     if (leaves == 0) return LJ_ERR_ARG;
-    if ((flags & ~7u) || ((flags & 3u) != LJ_LEAF_FP32 && (flags & 3u) != LJ_LEAF_FP64))
+    if ((flags & ~15u) || ((flags & 3u) != LJ_LEAF_FP32 && (flags & 3u) != LJ_LEAF_FP64))
         return LJ_ERR_ARG;
     if (n >= kMaxN || leaves > kMaxLeaves) return LJ_ERR_TOO_LARGE;
     for (uint64_t i = 1; i < n; ++i)
@@ -103,18 +103,28 @@ int lj_build_rmi(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves, uint3
                                              : (const void*)idx->leaf64.data();
     const uint64_t lbytes = (uint64_t)leaves * (lj::leaf_fp32(flags) ? sizeof(lj::LeafF32)
                                                                       : sizeof(lj::LeafF64));
+    const uint64_t fbytes = idx->fences.size() * sizeof(uint64_t);
+    const uint64_t bbytes = idx->bucket_lo.size() * sizeof(uint16_t);
     if (hipMalloc((void**)&idx->r_dev, rbytes) != hipSuccess ||
-        hipMalloc(&idx->leaf_dev, lbytes) != hipSuccess) {
+        hipMalloc(&idx->leaf_dev, lbytes) != hipSuccess ||
+        (fbytes && hipMalloc((void**)&idx->fences_dev, fbytes) != hipSuccess) ||
+        (bbytes && hipMalloc((void**)&idx->bucket_lo_dev, bbytes) != hipSuccess)) {
         (void)hipGetLastError();
         lj_free_index(idx);
         return LJ_ERR_OOM;
     }
-    idx->device_bytes = rbytes + lbytes;
+    idx->device_bytes = rbytes + lbytes + fbytes + bbytes;
     hipError_t e = hipSuccess;
     if (n) e = hipMemcpyAsync(idx->r_dev, r_keys_host, n * sizeof(uint64_t),
                               hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(idx->leaf_dev, lsrc, lbytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && fbytes)
+        e = hipMemcpyAsync(idx->fences_dev, idx->fences.data(), fbytes, hipMemcpyHostToDevice,
+                           stream);
+    if (e == hipSuccess && bbytes)
+        e = hipMemcpyAsync(idx->bucket_lo_dev, idx->bucket_lo.data(), bbytes,
+                           hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
         lj_free_index(idx);
@@ -128,10 +138,14 @@ void lj_free_index(lj_index* idx) {
     if (!idx) return;
     if (idx->r_dev) (void)hipFree(idx->r_dev);
     if (idx->leaf_dev) (void)hipFree(idx->leaf_dev);
+    if (idx->fences_dev) (void)hipFree(idx->fences_dev);
+    if (idx->bucket_lo_dev) (void)hipFree(idx->bucket_lo_dev);
     delete idx;
 }
 
-uint64_t lj_probe_workspace_bytes(uint64_t m) { return lj::ws_bytes(m); }
+uint64_t lj_probe_workspace_bytes(const lj_index* idx, uint64_t m) {
+    return idx ? lj::ws_bytes(idx, m) : 0;
+}
 
 int lj_probe_set_timing_events(hipEvent_t start, hipEvent_t stop) {
     t_ev_start = start;
@@ -152,7 +166,8 @@ int lj_probe_join_async(const lj_index* idx, const uint64_t* s, uint64_t m, lj_p
     if (st != LJ_OK) return st;
     if (m == 0) return lj::launch_set_u64(count_dev, 0, stream) == hipSuccess ? LJ_OK
                                                                              : LJ_ERR_DEVICE;
-    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < lj::ws_bytes(m)) return LJ_ERR_WORKSPACE;
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < lj::ws_bytes(idx, m))
+        return LJ_ERR_WORKSPACE;
     hipError_t e = lj::launch_probe(idx, s, m, out, cap, count_dev, ws, stream, ev0, ev1);
     return e == hipSuccess ? LJ_OK : LJ_ERR_DEVICE;
 }
@@ -171,7 +186,7 @@ int lj_probe_join(const lj_index* idx, const uint64_t* s, uint64_t m, lj_pair* o
         *count_host = 0;
         return LJ_OK;
     }
-    const uint64_t need = lj::ws_bytes(m);
+    const uint64_t need = lj::ws_bytes(idx, m);
     if (!t_host_count) {
         if (hipHostMalloc((void**)&t_host_count, sizeof(uint64_t)) != hipSuccess) {
             t_host_count = nullptr;

@@ -137,7 +137,7 @@ int plan_create(const lj_batch_desc* descs, uint32_t k, const lj_batch_tuning* t
     for (uint32_t b = 0; b < k; ++b) {
         p->ws_off.push_back(off);
         p->kpl.push_back(t.keys_per_lane[lj::size_class(descs[b].m)]);
-        off = lj::align256(off + lj::ws_bytes(descs[b].m));
+        off = lj::align256(off + lj::ws_bytes(descs[b].index, descs[b].m));
     }
     // Longest-processing-time assignment of batches to branches.
     std::vector<uint32_t> order(k);

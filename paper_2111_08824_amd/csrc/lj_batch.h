@@ -15,7 +15,7 @@ void default_tuning(lj_batch_tuning* t);
 int validate_tuning(const lj_batch_tuning& t);
 int validate_descs(const lj_batch_desc* d, uint32_t k, int device);
 // Enqueue one batch (a fused probe, or zeroing the count of an empty batch)
-// with workspace `ws` of at least ws_bytes(d.m) bytes.
+// with workspace `ws` of at least ws_bytes(d.index, d.m) bytes.
 hipError_t enqueue_one(const lj_batch_desc& d, void* ws, uint32_t kpl, hipStream_t st);
 
 }  // namespace lj

@@ -179,6 +179,16 @@ int fit_rmi(const uint64_t* r, uint64_t n, uint32_t L, uint32_t flags, lj_index*
     }
     idx->max_mult = mm;
 
+    // Equi-depth key ranges of R for the binned probe.
+    if ((flags & LJ_PROBE_BINNED) && n > 0) {
+        idx->fences.resize(kBins - 1);
+        for (uint32_t i = 0; i + 1 < kBins; ++i)
+            idx->fences[i] = r[((uint64_t)(i + 1) * n) / kBins];
+        idx->bucket_lo.assign(kBuckets + 1, 0);
+        for (uint64_t f : idx->fences) idx->bucket_lo[key_bucket(f) + 1]++;
+        for (uint32_t b = 0; b < kBuckets; ++b) idx->bucket_lo[b + 1] += idx->bucket_lo[b];
+    }
+
     if (leaf_fp32(flags)) {
         fit_leaves(r, pos0, cnt, L, idx->leaf32);
         leaf_stats(idx->leaf32, idx);

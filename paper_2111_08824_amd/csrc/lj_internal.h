@@ -26,9 +26,17 @@ struct lj_index {
     double mean_window = 0.0;
     uint64_t max_window = 0;
 
+    // LJ_PROBE_BINNED: kBins - 1 fences, fences[i] = R[(i + 1) * n / kBins]
+    // (the bin of key x is the number of fences <= x), and per key bucket
+    // the number of fences in lower buckets (kBuckets + 1 entries)
+    std::vector<uint64_t> fences;
+    std::vector<uint16_t> bucket_lo;
+
     // device copies
     uint64_t* r_dev = nullptr;
     void* leaf_dev = nullptr;
+    uint64_t* fences_dev = nullptr;
+    uint16_t* bucket_lo_dev = nullptr;
     uint64_t device_bytes = 0;
 };
 
@@ -62,8 +70,92 @@ struct WsHeader {
 constexpr uint64_t kWsHeaderBytes = 256;
 
 inline uint64_t num_tiles(uint64_t m, uint64_t tile) { return (m + tile - 1) / tile; }
+inline uint64_t align_up256(uint64_t v) { return (v + 255) & ~255ull; }
 // Sized for the smallest tile, so one workspace fits every launch shape.
-inline uint64_t ws_bytes(uint64_t m) { return kWsHeaderBytes + num_tiles(m, kMinTile) * 8; }
+inline uint64_t ws_bytes_direct(uint64_t m) {
+    return kWsHeaderBytes + num_tiles(m, kMinTile) * 8;
+}
+
+// Binned probe (LJ_PROBE_BINNED): S is put in key order of kBins equi-depth
+// ranges of R by two stable partition passes over the two kDigitBits-bit
+// digits of the bin number, probed in that order, and the results are put
+// back in S order before emission.
+constexpr uint32_t kBinBits = 12;
+constexpr uint32_t kBins = 1u << kBinBits;  // kBins - 1 fences
+constexpr uint32_t kDigitBits = 6;
+constexpr uint32_t kDigits = 1u << kDigitBits;
+static_assert(2 * kDigitBits == kBinBits, "two partition passes cover the bin number");
+constexpr uint32_t kPartItems = 16;
+constexpr uint32_t kPartChunk = kBlock * kPartItems;  // keys per partition chunk
+constexpr uint32_t kScanTile = kBlock * 16;           // counts per scan tile
+constexpr uint32_t kXcds = 8;  // workgroups are dealt to the XCDs round-robin
+
+// Bucket of a key on a float-like scale (exponent and the next kBucketBits
+// bits), monotone in the key.  The index keeps, per bucket, the number of
+// fences in lower buckets, so a key's bin is found by searching only the
+// few fences of its own bucket.
+constexpr uint32_t kBucketBits = 8;
+constexpr uint32_t kBuckets = (64 - kBucketBits + 1) << kBucketBits;  // 14592
+__host__ __device__ inline uint32_t key_bucket(uint64_t x) {
+    const int e = 63 - clz64(x | 1);  // floor(log2 x); 0 for x <= 1
+    const uint32_t hi = ((uint32_t)(e - (int)kBucketBits + 1) << kBucketBits) |
+                        (uint32_t)((x >> (e >= (int)kBucketBits ? e - (int)kBucketBits : 0)) &
+                                   ((1u << kBucketBits) - 1));
+    return x < (1ull << kBucketBits) ? (uint32_t)x : hi;
+}
+
+// Byte offsets inside the workspace of a binned probe.  [0, ctrl_bytes) is
+// zeroed before every probe: the header (error flag, count), three scan
+// tile counters, the scans' status words and the per-chunk pair counts.
+// res2/res1/res0 (per-key results in bin, pass-1 and S order) reuse p1, p2
+// and p1 once those are dead.
+struct BinnedWs {
+    uint64_t scan_ctr, scan_st1, scan_st2, scan_st3, counts, ctrl_bytes;
+    uint64_t hist1, hist2, bins_s, bins_1, p1, p2, dest1, dest2, total;
+};
+inline BinnedWs binned_ws(uint64_t m) {
+    BinnedWs L{};
+    const uint64_t nchunks = num_tiles(m, kPartChunk);
+    const uint64_t nh = (uint64_t)kDigits * nchunks;
+    const uint64_t nscan = num_tiles(nh, kScanTile);
+    uint64_t a = kWsHeaderBytes;
+    L.scan_ctr = a;
+    a += 256;
+    L.scan_st1 = a;
+    a = align_up256(a + nscan * 8);
+    L.scan_st2 = a;
+    a = align_up256(a + nscan * 8);
+    L.scan_st3 = a;
+    a = align_up256(a + num_tiles(nchunks + 1, kScanTile) * 8);
+    L.counts = a;  // pairs per chunk of S, then their exclusive prefix (+ total)
+    a = align_up256(a + (nchunks + 1) * 8);
+    L.ctrl_bytes = a;
+    L.hist1 = a;
+    a = align_up256(a + nh * 4);
+    L.hist2 = a;
+    a = align_up256(a + nh * 4);
+    L.bins_s = a;
+    a = align_up256(a + m * 2);
+    L.bins_1 = a;
+    a = align_up256(a + m * 2);
+    L.p1 = a;
+    a = align_up256(a + m * 8);
+    L.p2 = a;
+    a = align_up256(a + m * 8);
+    L.dest1 = a;
+    a = align_up256(a + m * 4);
+    L.dest2 = a;
+    a = align_up256(a + m * 4);
+    L.total = a;
+    return L;
+}
+inline bool uses_binned(const lj_index* idx, uint64_t m) {
+    return (idx->flags & LJ_PROBE_BINNED) && idx->n > 0 && m > 0;
+}
+// Workspace of one probe of m keys against idx.
+inline uint64_t ws_bytes(const lj_index* idx, uint64_t m) {
+    return uses_binned(idx, m) ? binned_ws(m).total : ws_bytes_direct(m);
+}
 
 // Everything the device needs to probe the tiles of one batch of outer keys
 // against one index.
@@ -99,7 +191,20 @@ bool probe_kpl_supported(uint32_t kpl, bool dup);
 hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m,
                         lj_pair* out, uint64_t cap, uint64_t* count_dev,
                         void* ws, hipStream_t stream, hipEvent_t ev0,
-                        hipEvent_t ev1, uint32_t kpl = 0);
+                        hipEvent_t ev1, uint32_t kpl = 0);  // kpl: direct probe only
+// Binned probe pieces (lj_partition.hip): the two partition passes of S
+// into the workspace laid out by binned_ws(m); out[p] = in[dest[p]] over m
+// elements of 4 bytes (8 with `wide`); the same with the number of pairs of
+// each chunk of kPartChunk outputs added to counts[chunk] (4-byte elements:
+// 1 unless ~0u; 8-byte: the high word), followed by the exclusive prefix of
+// counts[0 .. nchunks] in place, so counts[nchunks] = total.
+hipError_t launch_partition(const lj_index* idx, const uint64_t* s, uint64_t m, void* ws,
+                            const BinnedWs& layout, hipStream_t stream);
+hipError_t launch_unpermute(const uint32_t* dest, const void* in, void* out, uint64_t m,
+                            bool wide, hipStream_t stream);
+hipError_t launch_unpermute_count(const uint32_t* dest, const void* in, void* out, uint64_t m,
+                                  bool wide, void* ws, const BinnedWs& layout,
+                                  hipStream_t stream);
 hipError_t launch_set_u64(uint64_t* p, uint64_t v, hipStream_t stream);
 hipError_t launch_zero_words(uint64_t* p, uint64_t nwords, hipStream_t stream);
 hipError_t launch_self_check(const lj_index* idx, uint64_t* violations_dev,

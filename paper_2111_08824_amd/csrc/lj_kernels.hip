@@ -31,37 +31,11 @@
 // touch, the pairs, and 8 bytes of status per tile.
 #include <hip/hip_runtime.h>
 
+#include "lj_device.h"
 #include "lj_internal.h"
 
 namespace lj {
 namespace {
-
-constexpr uint64_t kFlagAgg = 1ull << 62;
-constexpr uint64_t kFlagInc = 2ull << 62;
-constexpr uint64_t kValMask = (1ull << 62) - 1;
-constexpr uint32_t kSpinLimit = 1u << 24;  // ~0.5 s of s_sleep before giving up
-
-__device__ inline uint64_t ld_status(const uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void st_status(uint64_t* p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ inline uint64_t wave_sum(uint64_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
-}
-
-__device__ inline uint64_t wave_incl_scan(uint64_t v, int lane) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint64_t t = __shfl_up(v, d, 64);
-        if (lane >= d) v += t;
-    }
-    return v;
-}
 
 // Leaf records are read as whole 16-byte vectors.
 __device__ inline LeafF32 load_leaf(const LeafF32* p) {
@@ -93,48 +67,6 @@ __device__ inline LeafF64 load_leaf(const LeafF64* p) {
     return l;
 }
 
-// Decoupled look-back, run by wave 0 of the block.  Publishes the tile's
-// aggregate, accumulates the predecessors' values until one with an
-// inclusive prefix is found, publishes the tile's inclusive prefix and
-// returns its exclusive prefix (valid in every lane of wave 0).
-__device__ uint64_t look_back(uint64_t* status, uint32_t tile, uint64_t total,
-                              uint32_t* err, int lane) {
-    if (tile == 0) {
-        if (lane == 0) st_status(&status[0], kFlagInc | total);
-        return 0;
-    }
-    if (lane == 0) st_status(&status[tile], kFlagAgg | total);
-    uint64_t excl = 0;
-    int64_t base = (int64_t)tile - 1;
-    for (;;) {
-        int64_t idx = base - lane;
-        uint64_t st = idx >= 0 ? ld_status(&status[idx]) : kFlagInc;
-        uint32_t spins = 0;
-        while (__ballot((st >> 62) == 0)) {
-            if ((st >> 62) == 0) st = ld_status(&status[idx]);
-            if (++spins > kSpinLimit) {
-                // A predecessor never published: report and stop waiting so
-                // that the kernel still exits.
-                if ((st >> 62) == 0) {
-                    atomicOr(err, 1u);
-                    st = kFlagInc;
-                }
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        uint64_t inc = __ballot((st >> 62) == 2);
-        if (inc) {
-            int first = __ffsll((unsigned long long)inc) - 1;
-            excl += wave_sum(lane <= first ? (st & kValMask) : 0);
-            break;
-        }
-        excl += wave_sum(st & kValMask);
-        base -= 64;
-    }
-    if (lane == 0) st_status(&status[tile], kFlagInc | (excl + total));
-    return excl;
-}
-
 // Shared memory of one tile; the duplicate path needs the per-key offsets
 // and first positions, the unique path only the per-wave counts.
 template <int kItems, bool kWithOffsets>
@@ -160,21 +92,20 @@ __device__ void finish_tile(const TileJob& j) {
     }
 }
 
-// Probe one tile of a batch: kBlock threads, the first `kpl` (<= kItems) keys
-// of each lane are live; key k of thread t is outer key
-// tile*kBlock*kpl + k*kBlock + t.
-template <class Leaf, bool kUnique, int kItems, bool kWithOffsets, bool kExp>
-__device__ void probe_tile(const TileJob& j, const uint32_t tile, const uint32_t kpl,
-                           TileShared<kItems, kWithOffsets>& sh) {
-    static_assert(kUnique || kWithOffsets, "the duplicate path needs LDS offsets");
+// Steps 1-4 for the keys of one tile: kBlock threads, the first `kpl`
+// (<= kItems) keys of each lane are live; key k of thread t is
+// s[tbase + k*kBlock + t].  On return first[k] is the lower bound of the key
+// in R (inside its window) and c[k] the number of R keys equal to it (0 for
+// a miss or a key past the end of s).
+template <class Leaf, bool kUnique, int kItems, bool kExp>
+__device__ __forceinline__ void search_keys(const uint64_t* __restrict__ R, const Leaf* leaves,
+                                            const RootModel& root, const uint64_t* s,
+                                            const uint64_t m, const uint64_t tbase,
+                                            const uint32_t kpl, uint32_t (&first)[kItems],
+                                            uint32_t (&c)[kItems]) {
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const uint64_t tbase = (uint64_t)tile * kBlock * kpl;
-    const Leaf* leaves = (const Leaf*)j.leaves;
-    const uint64_t* __restrict__ R = j.r;
     uint64_t x[kItems];
-    uint32_t first[kItems], len[kItems];  // binary search: window start, length
+    uint32_t len[kItems];  // binary search: window length
     int32_t lo[kExp ? kItems : 1], hi[kExp ? kItems : 1];  // exponential search:
     uint32_t pos[kExp ? kItems : 1], stp[kExp ? kItems : 1];  // bracket, probe, step|phase
     uint32_t end[kUnique ? 1 : kItems];
@@ -186,10 +117,10 @@ __device__ void probe_tile(const TileJob& j, const uint32_t tile, const uint32_t
     uint32_t validmask = 0;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        uint64_t s = tbase + (uint64_t)k * kBlock + tid;
-        const bool ok = (uint32_t)k < kpl && s < j.m;
+        const uint64_t q = tbase + (uint64_t)k * kBlock + tid;
+        const bool ok = (uint32_t)k < kpl && q < m;
         validmask |= (ok ? 1u : 0u) << k;
-        x[k] = j.s[ok ? s : j.m - 1];
+        x[k] = s[ok ? q : m - 1];
     }
     // 2: root model, leaf record, leaf model, window; kSetupChunk records
     // in flight at a time to bound register use.
@@ -197,7 +128,7 @@ __device__ void probe_tile(const TileJob& j, const uint32_t tile, const uint32_t
     for (int k0 = 0; k0 < kItems; k0 += kSetupChunk) {
         Leaf lf[kSetupChunk];
 #pragma unroll
-        for (int u = 0; u < kSetupChunk; ++u) lf[u] = load_leaf(leaves + route(j.root, x[k0 + u]));
+        for (int u = 0; u < kSetupChunk; ++u) lf[u] = load_leaf(leaves + route(root, x[k0 + u]));
 #pragma unroll
         for (int u = 0; u < kSetupChunk; ++u) {
             const int k = k0 + u;
@@ -302,7 +233,6 @@ __device__ void probe_tile(const TileJob& j, const uint32_t tile, const uint32_t
     }
 
     // 4: run lengths.
-    uint32_t c[kItems];
 #pragma unroll
     for (int k = 0; k < kItems; ++k) c[k] = (eqmask >> k) & 1u;
     if constexpr (!kUnique) {
@@ -346,7 +276,24 @@ __device__ void probe_tile(const TileJob& j, const uint32_t tile, const uint32_t
             }
         }
     }
+}
 
+// Steps 5-7 for one tile whose lower bounds and run lengths are known:
+// offsets, look-back, pair emission; then the tile is counted as done.
+// Without kLookBack the tile's output offset is given (excl_given) and the
+// batch total is written elsewhere.
+template <bool kUnique, int kItems, bool kWithOffsets, bool kLookBack = true>
+__device__ __forceinline__ void emit_tile(const TileJob& j, const uint32_t tile,
+                                          const uint32_t kpl,
+                                          TileShared<kItems, kWithOffsets>& sh,
+                                          const uint32_t (&first)[kItems],
+                                          const uint32_t (&c)[kItems],
+                                          const uint64_t excl_given = 0) {
+    static_assert(kUnique || kWithOffsets, "the duplicate path needs LDS offsets");
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const uint64_t tbase = (uint64_t)tile * kBlock * kpl;
     if constexpr (kUnique) {
         // 5: ballot/popcount offsets; key order in the tile is (k, wave, lane).
         uint32_t lane_off[kItems];
@@ -362,9 +309,13 @@ __device__ void probe_tile(const TileJob& j, const uint32_t tile, const uint32_t
 #pragma unroll
         for (int q = 0; q < kItems * (kBlock / 64); ++q) total += sh.wsum[q];
         // 6: look-back.
-        if (wave == 0) {
-            uint64_t e = look_back(j.status, tile, total, j.err, lane);
-            if (lane == 0) sh.excl = e;
+        if constexpr (kLookBack) {
+            if (wave == 0) {
+                uint64_t e = look_back(j.status, tile, total, j.err, lane);
+                if (lane == 0) sh.excl = e;
+            }
+        } else {
+            if (tid == 0) sh.excl = excl_given;
         }
         __syncthreads();
         const uint64_t excl = sh.excl;
@@ -416,9 +367,13 @@ __device__ void probe_tile(const TileJob& j, const uint32_t tile, const uint32_t
         for (int i = 0; i < kItems; ++i) sh.off[tid * kItems + i] = texcl + loc[i];
         if (tid == 0) sh.off[(kBlock * kItems)] = total;
         // 6: look-back.
-        if (wave == 0) {
-            uint64_t e = look_back(j.status, tile, total, j.err, lane);
-            if (lane == 0) sh.excl = e;
+        if constexpr (kLookBack) {
+            if (wave == 0) {
+                uint64_t e = look_back(j.status, tile, total, j.err, lane);
+                if (lane == 0) sh.excl = e;
+            }
+        } else {
+            if (tid == 0) sh.excl = excl_given;
         }
         __syncthreads();
         const uint64_t excl = sh.excl;
@@ -441,7 +396,18 @@ __device__ void probe_tile(const TileJob& j, const uint32_t tile, const uint32_t
         }
     }
     __syncthreads();  // the block's LDS is reused by the next tile
-    finish_tile(j);
+    if constexpr (kLookBack) finish_tile(j);
+}
+
+// Probe one tile of a batch (steps 1-7).
+template <class Leaf, bool kUnique, int kItems, bool kWithOffsets, bool kExp>
+__device__ __forceinline__ void probe_tile(const TileJob& j, const uint32_t tile,
+                                           const uint32_t kpl,
+                                           TileShared<kItems, kWithOffsets>& sh) {
+    uint32_t first[kItems], c[kItems];
+    search_keys<Leaf, kUnique, kItems, kExp>(j.r, (const Leaf*)j.leaves, j.root, j.s, j.m,
+                                             (uint64_t)tile * kBlock * kpl, kpl, first, c);
+    emit_tile<kUnique, kItems, kWithOffsets>(j, tile, kpl, sh, first, c);
 }
 
 template <class Leaf, bool kUnique, int kItems, bool kExp>
@@ -451,6 +417,69 @@ __global__ __launch_bounds__(kBlock) void probe_join_kernel(TileJob j, uint32_t*
     if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
     __syncthreads();
     probe_tile<Leaf, kUnique, kItems, !kUnique, kExp>(j, s_tile, kItems, sh);
+}
+
+// Search kernel of the binned probe: keys in bin order, tiles of kBlock *
+// kItems keys; the tiles are split into kXcds contiguous ranges and
+// workgroup g works on range g % kXcds, so that each XCD's L2 holds the R
+// lines of its own few key ranges.  res[q] = lower bound of keys[q] when
+// found, else ~0u (unique R); res[q] = lower bound | count << 32, or 0
+// (duplicates).
+template <class Leaf, bool kUnique, int kItems, bool kExp>
+__global__ __launch_bounds__(kBlock) void probe_binned_kernel(const uint64_t* __restrict__ R,
+                                                              const Leaf* leaves,
+                                                              RootModel root,
+                                                              const uint64_t* keys, uint64_t m,
+                                                              uint32_t ntiles,
+                                                              uint32_t tiles_per_xcd,
+                                                              void* res) {
+    const uint32_t slot = blockIdx.x / kXcds;
+    const uint32_t tile = (blockIdx.x % kXcds) * tiles_per_xcd + slot;
+    if (slot >= tiles_per_xcd || tile >= ntiles) return;
+    const uint64_t tbase = (uint64_t)tile * kBlock * kItems;
+    uint32_t first[kItems], c[kItems];
+    search_keys<Leaf, kUnique, kItems, kExp>(R, leaves, root, keys, m, tbase, kItems, first, c);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const uint64_t q = tbase + (uint64_t)k * kBlock + threadIdx.x;
+        if (q >= m) continue;
+        if constexpr (kUnique) ((uint32_t*)res)[q] = c[k] ? first[k] : ~0u;
+        else ((uint64_t*)res)[q] = c[k] ? (uint64_t)first[k] | ((uint64_t)c[k] << 32) : 0ull;
+    }
+}
+
+// Emission kernel of the binned probe: per-key results in S order (layout
+// of probe_binned_kernel), one chunk of kPartChunk keys per block, the
+// chunk's output offset from the scanned per-chunk pair counts -> steps 5
+// and 7 of the fused probe, with no wait on other blocks.
+template <bool kUnique>
+__global__ __launch_bounds__(kBlock) void emit_chunks_kernel(TileJob j, const void* res,
+                                                             const uint64_t* offs) {
+    constexpr int kItems = (int)kPartItems;
+    __shared__ TileShared<kItems, !kUnique> sh;
+    const uint32_t tile = blockIdx.x;
+    const uint64_t tbase = (uint64_t)tile * kPartChunk;
+    uint32_t first[kItems], c[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const uint64_t q = tbase + (uint64_t)k * kBlock + threadIdx.x;
+        if constexpr (kUnique) {
+            const uint32_t v = q < j.m ? ((const uint32_t*)res)[q] : ~0u;
+            first[k] = v;
+            c[k] = v != ~0u ? 1u : 0u;
+        } else {
+            const uint64_t v = q < j.m ? ((const uint64_t*)res)[q] : 0ull;
+            first[k] = (uint32_t)v;
+            c[k] = (uint32_t)(v >> 32);
+        }
+    }
+    emit_tile<kUnique, kItems, !kUnique, false>(j, tile, kItems, sh, first, c, offs[tile]);
+}
+
+// Total of the binned probe, or UINT64_MAX after a wait error.
+__global__ void finish_binned_kernel(const uint64_t* total, const uint32_t* err,
+                                     uint64_t* count_out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *count_out = *err ? ~0ull : *total;
 }
 
 __global__ void zero_words(uint64_t* w, uint64_t nwords) {
@@ -559,9 +588,93 @@ bool probe_kpl_supported(uint32_t kpl, bool dup) {
     return kpl == 4 || kpl == 8 || kpl == 16 || (!dup && kpl == 24);
 }
 
+namespace {
+
+template <class Leaf, bool kUnique, bool kExp>
+void launch_binned_search(const lj_index* idx, const uint64_t* keys, uint64_t m, void* res,
+                          hipStream_t stream) {
+    constexpr int kItems = kUnique ? kItemsUnique : kItemsDup;
+    const uint32_t nt = (uint32_t)num_tiles(m, (uint64_t)kBlock * kItems);
+    const uint32_t per = (nt + kXcds - 1) / kXcds;
+    hipLaunchKernelGGL((probe_binned_kernel<Leaf, kUnique, kItems, kExp>), dim3(per * kXcds),
+                       dim3(kBlock), 0, stream, idx->r_dev, (const Leaf*)idx->leaf_dev,
+                       idx->root, keys, m, nt, per, res);
+}
+
+// Binned probe: partition S by key range, search in that order, put the
+// per-key results back in S order, emit.
+hipError_t launch_probe_binned(const lj_index* idx, const uint64_t* s, uint64_t m,
+                               lj_pair* out, uint64_t cap, uint64_t* count_dev, void* ws,
+                               hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
+    const uint32_t kind = job_kind(idx);
+    const bool dup = (kind & kJobDup) != 0;
+    const BinnedWs L = binned_ws(m);
+    char* w = (char*)ws;
+    hipError_t e = launch_zero_words((uint64_t*)ws, L.ctrl_bytes / 8, stream);
+    if (e != hipSuccess) return e;
+    e = launch_partition(idx, s, m, ws, L, stream);
+    if (e != hipSuccess) return e;
+    // res2 (bin order) in p1, res1 (pass-1 order) in p2, res0 (S order) in p1.
+    void* res2 = w + L.p1;
+    void* res1 = w + L.p2;
+    void* res0 = w + L.p1;
+    const uint64_t* keys = (const uint64_t*)(w + L.p2);
+    if (ev0) {
+        e = hipEventRecord(ev0, stream);
+        if (e != hipSuccess) return e;
+    }
+    const bool ex = (kind & kJobExp) != 0;
+    const bool f64 = (kind & kJobFp64) != 0;
+    if (!f64 && !dup) ex ? launch_binned_search<LeafF32, true, true>(idx, keys, m, res2, stream)
+                         : launch_binned_search<LeafF32, true, false>(idx, keys, m, res2, stream);
+    else if (!f64) ex ? launch_binned_search<LeafF32, false, true>(idx, keys, m, res2, stream)
+                      : launch_binned_search<LeafF32, false, false>(idx, keys, m, res2, stream);
+    else if (!dup) ex ? launch_binned_search<LeafF64, true, true>(idx, keys, m, res2, stream)
+                      : launch_binned_search<LeafF64, true, false>(idx, keys, m, res2, stream);
+    else ex ? launch_binned_search<LeafF64, false, true>(idx, keys, m, res2, stream)
+            : launch_binned_search<LeafF64, false, false>(idx, keys, m, res2, stream);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ev1) {
+        e = hipEventRecord(ev1, stream);
+        if (e != hipSuccess) return e;
+    }
+    e = launch_unpermute((const uint32_t*)(w + L.dest2), res2, res1, m, dup, stream);
+    if (e == hipSuccess)
+        e = launch_unpermute_count((const uint32_t*)(w + L.dest1), res1, res0, m, dup, ws, L,
+                                   stream);
+    if (e != hipSuccess) return e;
+
+    const uint64_t* offs = (const uint64_t*)(w + L.counts);
+    WsHeader* hdr = (WsHeader*)ws;
+    TileJob j{};
+    j.s = s;
+    j.m = m;
+    j.out = out;
+    j.cap = out ? cap : 0;
+    j.count_out = count_dev;
+    j.err = &hdr->err;
+    j.ntiles = (uint32_t)num_tiles(m, kPartChunk);
+    j.kind = kind;
+    j.kpl = kPartItems;
+    if (dup)
+        hipLaunchKernelGGL(emit_chunks_kernel<false>, dim3(j.ntiles), dim3(kBlock), 0, stream, j,
+                           (const void*)res0, offs);
+    else
+        hipLaunchKernelGGL(emit_chunks_kernel<true>, dim3(j.ntiles), dim3(kBlock), 0, stream, j,
+                           (const void*)res0, offs);
+    hipLaunchKernelGGL(finish_binned_kernel, dim3(1), dim3(64), 0, stream, offs + j.ntiles,
+                       (const uint32_t*)&hdr->err, count_dev);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m, lj_pair* out,
                         uint64_t cap, uint64_t* count_dev, void* ws, hipStream_t stream,
                         hipEvent_t ev0, hipEvent_t ev1, uint32_t kpl) {
+    if (uses_binned(idx, m))
+        return launch_probe_binned(idx, s, m, out, cap, count_dev, ws, stream, ev0, ev1);
     const uint32_t kind = job_kind(idx);
     if (kpl == 0) kpl = (kind & kJobDup) ? kItemsDup : kItemsUnique;
     if (!probe_kpl_supported(kpl, (kind & kJobDup) != 0)) return hipErrorInvalidValue;

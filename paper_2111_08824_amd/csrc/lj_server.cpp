@@ -126,7 +126,7 @@ uint64_t footprint(const lj_index* idx, uint64_t m, uint64_t cap, Request* r) {
     uint64_t out_off = off;
     off = lj::align256(off + 8 * devcap);
     uint64_t ws_off = off;
-    off = lj::align256(off + lj::ws_bytes(m));
+    off = lj::align256(off + lj::ws_bytes(idx, m));
     uint64_t cnt_off = off;
     off = lj::align256(off + 8);
     if (r) {

@@ -30,6 +30,7 @@ LJ_ERR_TIMEOUT = -8
 LJ_LEAF_FP32 = 1
 LJ_LEAF_FP64 = 2
 LJ_SEARCH_EXPONENTIAL = 4
+LJ_PROBE_BINNED = 8
 
 EXPORTED = (
     "lj_build_rmi", "lj_free_index", "lj_probe_join", "lj_probe_workspace_bytes",
@@ -139,7 +140,7 @@ def lib() -> ctypes.CDLL:
         L.lj_free_index.argtypes = [vp]
         L.lj_free_index.restype = None
         L.lj_probe_join.argtypes = [vp, vp, u64, vp, u64, ctypes.POINTER(u64), vp]
-        L.lj_probe_workspace_bytes.argtypes = [u64]
+        L.lj_probe_workspace_bytes.argtypes = [vp, u64]
         L.lj_probe_workspace_bytes.restype = u64
         L.lj_probe_join_async.argtypes = [vp, vp, u64, vp, u64, vp, vp, u64, vp]
         L.lj_index_get_stats.argtypes = [vp, ctypes.POINTER(lj_index_stats)]
@@ -269,8 +270,8 @@ def lj_probe_join(index: Index, s_keys_dev, out_pairs_dev=None, stream=None):
     return st, cnt.value
 
 
-def lj_probe_workspace_bytes(m: int) -> int:
-    return int(lib().lj_probe_workspace_bytes(m))
+def lj_probe_workspace_bytes(index: Index, m: int) -> int:
+    return int(lib().lj_probe_workspace_bytes(index.handle, m))
 
 
 def lj_probe_join_async(index: Index, s_keys_dev, out_pairs_dev, count_dev, workspace_dev,

@@ -1,5 +1,6 @@
 """Full-size parity on the lognormal / Zipf workload (2e8 x 2e8, 2^20 leaves),
-probed the way the benchmark probes it (FP32 leaves, synchronous probe).
+probed the way the benchmark probes it (FP32 leaves, synchronous probe, with
+and without the binned probe).
 
 The oracle's full sort-merge is too slow on the host at this size, so the
 output is checked by properties that pin it exactly:
@@ -19,14 +20,32 @@ import workloads
 from paper_2111_08824_amd import lj
 
 pytestmark = pytest.mark.gpu
+MODES = [lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP32 | lj.LJ_PROBE_BINNED]
 
 
-def test_lognormal_zipf_200m_full_size():
-    import torch
+@pytest.fixture(scope="module")
+def c2():
     print("[fullsize] generating lognormal-zipf-200M", flush=True)
-    w = workloads.c2_lognormal_zipf()
-    print("[fullsize] building index (fp32 leaves, 2^20)", flush=True)
-    ix = lj.lj_build_rmi(w.R, w.leaves, lj.LJ_LEAF_FP32)
+    return workloads.c2_lognormal_zipf()
+
+
+@pytest.fixture(scope="module")
+def c3():
+    print("[fullsize] generating dup-runs-100M", flush=True)
+    w = workloads.c3_dup_runs()
+    ur, cr = np.unique(w.R, return_counts=True)
+    us, cs = np.unique(w.S, return_counts=True)
+    _, ir, is_ = np.intersect1d(ur, us, assume_unique=True, return_indices=True)
+    want = int(np.sum(cr[ir].astype(np.int64) * cs[is_].astype(np.int64)))
+    return w, want
+
+
+@pytest.mark.parametrize("flags", MODES)
+def test_lognormal_zipf_200m_full_size(c2, flags):
+    import torch
+    w = c2
+    print(f"[fullsize] building index (fp32 leaves, 2^20, flags {flags})", flush=True)
+    ix = lj.lj_build_rmi(w.R, w.leaves, flags)
     assert lj.lj_self_check(ix) == 0
     s = lj.to_device_keys(w.S)
     out = torch.empty((len(w.S), 2), dtype=torch.int32, device="cuda")
@@ -50,7 +69,8 @@ def test_lognormal_zipf_200m_full_size():
     assert np.array_equal(ri[pos_c][emitted], first[emitted].astype(np.int64))
 
 
-def test_dup_runs_100m_full_size():
+@pytest.mark.parametrize("flags", MODES)
+def test_dup_runs_100m_full_size(c3, flags):
     """1e8 rows of seq_h values repeated U{1..16} times, 1e8 outer keys with
     70% hits: about 6e8 pairs.  Exact by: every pair matches, pairs strictly
     increase in (s, r), and their number equals the count invariant
@@ -58,16 +78,10 @@ def test_dup_runs_100m_full_size():
     GPU path and the oracle's merge); plus 100,000 sampled keys against the
     oracle's equal_range."""
     import torch
-    print("[fullsize] generating dup-runs-100M", flush=True)
-    w = workloads.c3_dup_runs()
-    ur, cr = np.unique(w.R, return_counts=True)
-    us, cs = np.unique(w.S, return_counts=True)
-    _, ir, is_ = np.intersect1d(ur, us, assume_unique=True, return_indices=True)
-    want = int(np.sum(cr[ir].astype(np.int64) * cs[is_].astype(np.int64)))
-    del ur, cr, us, cs
-    print(f"[fullsize] building index (fp32 leaves, {w.leaves}); expecting {want} pairs",
-          flush=True)
-    ix = lj.lj_build_rmi(w.R, w.leaves, lj.LJ_LEAF_FP32)
+    w, want = c3
+    print(f"[fullsize] building index (fp32 leaves, {w.leaves}, flags {flags}); "
+          f"expecting {want} pairs", flush=True)
+    ix = lj.lj_build_rmi(w.R, w.leaves, flags)
     assert lj.lj_self_check(ix) == 0
     s = lj.to_device_keys(w.S)
     out = torch.empty((want, 2), dtype=torch.int32, device="cuda")

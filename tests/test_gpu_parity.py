@@ -17,7 +17,9 @@ pytestmark = pytest.mark.gpu
 U64MAX = 2**64 - 1
 FLAGS = [lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP64]
 EXP = lj.LJ_SEARCH_EXPONENTIAL
-ALL_FLAGS = FLAGS + [lj.LJ_LEAF_FP32 | EXP, lj.LJ_LEAF_FP64 | EXP]
+BIN = lj.LJ_PROBE_BINNED
+ALL_FLAGS = FLAGS + [lj.LJ_LEAF_FP32 | EXP, lj.LJ_LEAF_FP64 | EXP, lj.LJ_LEAF_FP32 | BIN,
+                     lj.LJ_LEAF_FP64 | BIN, lj.LJ_LEAF_FP32 | EXP | BIN]
 
 
 def gpu_join(R, S, leaves, flags, capacity=None):
@@ -59,7 +61,7 @@ def test_dup_runs_1m(flags):
 
 
 @pytest.mark.parametrize("m", [1, 2, 63, 64, 255, 1023, 1024, 1025, 4096 + 7, 77_777])
-@pytest.mark.parametrize("search", [0, EXP])
+@pytest.mark.parametrize("search", [0, EXP, BIN])
 def test_ragged_tile_tails(m, search):
     R = workloads.gen.uniform_unique(50_000, 20, 3)
     S = workloads.gen.probe_mix(R, m, 0.6, 4, miss_hi=2**20)
@@ -67,7 +69,7 @@ def test_ragged_tile_tails(m, search):
 
 
 @pytest.mark.parametrize("leaves", [1, 2, 1000, 200_003])
-@pytest.mark.parametrize("search", [0, EXP])
+@pytest.mark.parametrize("search", [0, EXP, BIN])
 def test_leaf_counts(leaves, search):
     R = workloads.gen.lognormal_unique(50_000, 2.0, 5)
     S = workloads.gen.probe_mix(R, 60_000, 0.5, 6, miss_hi=2**63)
@@ -84,13 +86,24 @@ def test_heavy_duplicates_load_balanced_emission():
     assert len(got) == 3 * 5000 + 2
     got = assert_parity(R, S, 8, lj.LJ_LEAF_FP32 | EXP, "heavy duplicates, exponential")
     assert len(got) == 3 * 5000 + 2
+    got = assert_parity(R, S, 8, lj.LJ_LEAF_FP32 | BIN, "heavy duplicates, binned")
+    assert len(got) == 3 * 5000 + 2
 
 
-def test_all_equal_inner_relation():
+@pytest.mark.parametrize("flags", [lj.LJ_LEAF_FP64, lj.LJ_LEAF_FP64 | BIN])
+def test_all_equal_inner_relation(flags):
     R = np.full(3000, 42, dtype=np.uint64)
     S = np.array([42, 41, 43, 42], dtype=np.uint64)
-    got = assert_parity(R, S, 16, lj.LJ_LEAF_FP64, "all equal")
+    got = assert_parity(R, S, 16, flags, "all equal")
     assert len(got) == 6000
+
+
+@pytest.mark.parametrize("n", [1, 2, 4095, 4096, 4097])
+def test_binned_small_inner_relations(n):
+    # Fewer keys in R than key ranges: most ranges are empty or share a fence.
+    R = workloads.gen.uniform_unique(n, 24, 11)
+    S = workloads.gen.probe_mix(R, 30_000, 0.7, 12, miss_hi=2**24)
+    assert_parity(R, S, max(1, n // 64), lj.LJ_LEAF_FP32 | BIN, f"binned n={n}")
 
 
 def test_extreme_keys():
@@ -100,26 +113,28 @@ def test_extreme_keys():
         assert_parity(R, S, 3, flags, "extreme keys")
 
 
-def test_all_misses_and_empty_inputs():
+@pytest.mark.parametrize("binned", [0, BIN])
+def test_all_misses_and_empty_inputs(binned):
     R = workloads.gen.uniform_unique(10_000, 30, 8)
     S = np.array([2**40 + i for i in range(5000)], dtype=np.uint64)
-    got = assert_parity(R, S, 64, lj.LJ_LEAF_FP32, "all misses")
+    got = assert_parity(R, S, 64, lj.LJ_LEAF_FP32 | binned, "all misses")
     assert len(got) == 0
     # m = 0
-    ix = lj.lj_build_rmi(R, 64)
+    ix = lj.lj_build_rmi(R, 64, lj.LJ_LEAF_FP32 | binned)
     s0 = lj.to_device_keys(np.empty(0, dtype=np.uint64))
     assert lj.lj_probe_join(ix, s0) == (lj.LJ_OK, 0)
     # n = 0
-    ix0 = lj.lj_build_rmi(np.empty(0, dtype=np.uint64), 4)
+    ix0 = lj.lj_build_rmi(np.empty(0, dtype=np.uint64), 4, lj.LJ_LEAF_FP32 | binned)
     s = lj.to_device_keys(np.array([0, 1, U64MAX], dtype=np.uint64))
     assert lj.lj_probe_join(ix0, s) == (lj.LJ_OK, 0)
 
 
-def test_capacity_protocol():
+@pytest.mark.parametrize("binned", [0, BIN])
+def test_capacity_protocol(binned):
     import torch
     w = workloads.c3_dup_runs(scale=0.001)
     want = oracle.sort_merge_join(w.R, w.S)
-    ix = lj.lj_build_rmi(w.R, w.leaves)
+    ix = lj.lj_build_rmi(w.R, w.leaves, lj.LJ_LEAF_FP32 | binned)
     s = lj.to_device_keys(w.S)
     st, cnt = lj.lj_probe_join(ix, s, None)  # count only
     assert (st, cnt) == (lj.LJ_OK, len(want))
@@ -131,9 +146,10 @@ def test_capacity_protocol():
     assert np.array_equal(got, want[:cap])  # the first cap pairs, in order
 
 
-def test_split_invariance():
+@pytest.mark.parametrize("binned", [0, BIN])
+def test_split_invariance(binned):
     w = workloads.c2_lognormal_zipf(scale=0.005)
-    ix = lj.lj_build_rmi(w.R, w.leaves)
+    ix = lj.lj_build_rmi(w.R, w.leaves, lj.LJ_LEAF_FP32 | binned)
     whole = lj.probe(ix, lj.to_device_keys(w.S)).cpu().numpy().view(np.uint32)
     parts = []
     cuts = [0, 1, 1000, 1024 * 7 + 3, 400_000, len(w.S)]
@@ -144,13 +160,14 @@ def test_split_invariance():
     assert np.array_equal(np.concatenate(parts), whole)
 
 
-def test_async_matches_sync_and_checks_workspace():
+@pytest.mark.parametrize("binned", [0, BIN])
+def test_async_matches_sync_and_checks_workspace(binned):
     import torch
     w = workloads.c1_uniform(scale=0.2)
     want = oracle.sort_merge_join(w.R, w.S)
-    ix = lj.lj_build_rmi(w.R, w.leaves)
+    ix = lj.lj_build_rmi(w.R, w.leaves, lj.LJ_LEAF_FP32 | binned)
     s = lj.to_device_keys(w.S)
-    nbytes = lj.lj_probe_workspace_bytes(len(w.S))
+    nbytes = lj.lj_probe_workspace_bytes(ix, len(w.S))
     ws = torch.empty(nbytes // 8 + 1, dtype=torch.int64, device="cuda")
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
     out = torch.empty((len(want) + 5, 2), dtype=torch.int32, device="cuda")

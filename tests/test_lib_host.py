@@ -57,11 +57,28 @@ def test_argument_errors():
     assert _build_status(R, flags=3) == lj.LJ_ERR_ARG
     assert _build_status(R, flags=lj.LJ_SEARCH_EXPONENTIAL) == lj.LJ_ERR_ARG
     assert _build_status(R, flags=lj.LJ_LEAF_FP64 | lj.LJ_SEARCH_EXPONENTIAL) == lj.LJ_OK
-    assert _build_status(R, flags=lj.LJ_LEAF_FP32 | 8) == lj.LJ_ERR_ARG
+    assert _build_status(R, flags=lj.LJ_LEAF_FP32 | lj.LJ_PROBE_BINNED) == lj.LJ_OK
+    assert _build_status(R, flags=lj.LJ_LEAF_FP32 | 16) == lj.LJ_ERR_ARG
     assert _build_status(R, leaves=2**26 + 1) == lj.LJ_ERR_TOO_LARGE
     assert _build_status(R, n=2**31) == lj.LJ_ERR_TOO_LARGE  # checked before reading R
     h = ctypes.c_void_p()
     assert lj.lib().lj_build_rmi_host_only(None, 5, 4, 1, ctypes.byref(h)) == lj.LJ_ERR_ARG
+
+
+def test_workspace_sizes():
+    R = np.arange(1000, dtype=np.uint64)
+    direct = lj.lj_build_rmi_host_only(R, 4, lj.LJ_LEAF_FP32)
+    binned = lj.lj_build_rmi_host_only(R, 4, lj.LJ_LEAF_FP32 | lj.LJ_PROBE_BINNED)
+    empty = lj.lj_build_rmi_host_only(R[:0], 4, lj.LJ_LEAF_FP32 | lj.LJ_PROBE_BINNED)
+    assert lj.lib().lj_probe_workspace_bytes(None, 10) == 0
+    for m in (1, 4095, 4096, 10**6, 2**32 - 1):
+        d = lj.lj_probe_workspace_bytes(direct, m)
+        b = lj.lj_probe_workspace_bytes(binned, m)
+        assert d >= 256 + 8 * (m // 1024) and d % 8 == 0
+        # partitioned keys twice, destinations twice, bins twice: 28 B per key
+        assert b >= d + 28 * m and b % 256 == 0
+        assert lj.lj_probe_workspace_bytes(empty, m) == d  # n = 0 never partitions
+    assert lj.lj_probe_workspace_bytes(binned, 0) == lj.lj_probe_workspace_bytes(direct, 0)
 
 
 def test_probe_of_host_only_index_is_rejected():
