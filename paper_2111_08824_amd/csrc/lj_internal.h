@@ -55,6 +55,7 @@ int fit_rmi(const uint64_t* r, uint64_t n, uint32_t leaves, uint32_t flags,
 constexpr int kBlock = 256;
 constexpr int kItemsUnique = 24;
 constexpr int kItemsDup = 16;
+constexpr int kItemsBinned = 16;  // search kernel of the binned probe (measured best)
 constexpr int kSetupChunk = 4;
 constexpr int kMinTile = kBlock * 4;  // smallest tile any launch uses
 

@@ -214,20 +214,22 @@ __device__ __forceinline__ void search_keys(const uint64_t* __restrict__ R, cons
         // R[mid] >= x[k], so bit k of eqmask tells whether x[k] was found.
         for (;;) {
             uint32_t anylen = 0;
-    #pragma unroll
+#pragma unroll
             for (int k = 0; k < kItems; ++k) anylen |= len[k];
             if (!anylen) break;
             uint64_t v[kItems];
-    #pragma unroll
+#pragma unroll
             for (int k = 0; k < kItems; ++k) v[k] = R[len[k] ? first[k] + (len[k] >> 1) : 0];
-    #pragma unroll
+#pragma unroll
             for (int k = 0; k < kItems; ++k) {
                 const uint32_t half = len[k] >> 1;
-                const bool act = len[k] != 0;
-                const bool lt = v[k] < x[k];
-                first[k] = (act && lt) ? first[k] + half + 1 : first[k];
-                if (act && !lt) eqmask = (eqmask & ~(1u << k)) | ((v[k] == x[k] ? 1u : 0u) << k);
-                len[k] = act ? (lt ? len[k] - half - 1 : half) : 0;
+                const uint32_t act = len[k] != 0 ? 1u : 0u;
+                const uint32_t lt = v[k] < x[k] ? act : 0u;   // act && lt
+                const uint32_t ge = act ^ lt;                   // act && !lt
+                const uint32_t eq = v[k] == x[k] ? 1u : 0u;
+                first[k] += lt * (half + 1);
+                eqmask = (eqmask & ~(ge << k)) | ((eq & ge) << k);
+                len[k] = lt ? len[k] - half - 1 : half;
             }
         }
     }
@@ -593,7 +595,7 @@ namespace {
 template <class Leaf, bool kUnique, bool kExp>
 void launch_binned_search(const lj_index* idx, const uint64_t* keys, uint64_t m, void* res,
                           hipStream_t stream) {
-    constexpr int kItems = kUnique ? kItemsUnique : kItemsDup;
+    constexpr int kItems = kItemsBinned;
     const uint32_t nt = (uint32_t)num_tiles(m, (uint64_t)kBlock * kItems);
     const uint32_t per = (nt + kXcds - 1) / kXcds;
     hipLaunchKernelGGL((probe_binned_kernel<Leaf, kUnique, kItems, kExp>), dim3(per * kXcds),
