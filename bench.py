@@ -5,7 +5,9 @@ One step = one synchronous probe (lj_probe_join) of the whole outer relation
 S against the two-level linear RMI over R: root model, leaf model, bounded
 last-mile search, match counting, output compaction and pair emission, plus
 the 8-byte count readback.  R, the index and S are resident in HBM before
-the timed region; building the index is offline (untimed).
+the timed region; building the index is offline (untimed).  By default the
+probe is the binned one (S partitioned by key range of R first, the same
+pairs in the same order); --probe direct probes S in its own order.
 
 Default workload: R = 2e8 distinct lognormal(0, 2) keys scaled to 2^63,
 2^20 leaves with FP32 leaf models; S = 2e8 keys, 90% Zipf(1) hits.
@@ -316,7 +318,7 @@ def main():
     ap.add_argument("--leaf", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--search", choices=["binary", "exponential"], default="binary",
                     help="last-mile search inside the error bounds")
-    ap.add_argument("--probe", choices=["direct", "binned"], default="direct",
+    ap.add_argument("--probe", choices=["direct", "binned"], default="binned",
                     help="probe S in its own order, or partitioned by key range first")
     ap.add_argument("--cpu-sample", type=int, default=120_000_000,
                     help="outer keys in the timed oracle sample (0 = skip)")
