@@ -186,12 +186,16 @@ typedef struct {
  * {4, 8, 16, 24} (24 is lowered to 16 for indexes with duplicate keys).
  * `branches` (1..16) is the number of parallel streams the batches are
  * spread over; `use_graph` selects graph replay (1) or direct launches (0).
+ * `binned_min_keys`: batches of at least this many outer keys use the
+ * binned probe (LJ_PROBE_BINNED) and smaller ones the direct probe; 0 keeps
+ * each index's own choice, UINT64_MAX probes every batch directly.
  * `measured_ms` is filled by lj_batch_autotune.
  */
 typedef struct {
     uint32_t keys_per_lane[4];
     uint32_t branches;
     uint32_t use_graph;
+    uint64_t binned_min_keys;
     float measured_ms;
 } lj_batch_tuning;
 
@@ -220,8 +224,9 @@ int lj_batch_plan_run(lj_batch_plan* plan, hipStream_t stream);
 void lj_batch_plan_destroy(lj_batch_plan* plan);
 
 /*
- * Autotuner: times candidate launch shapes (branch counts and keys per
- * lane for each size class present) on the device with these descriptors,
+ * Autotuner: times candidate launch shapes (branch counts, the batch size
+ * from which the binned probe is used, and keys per lane for each size
+ * class present) on the device with these descriptors,
  * by coordinate descent from the default, and returns the fastest in
  * *tuning (measured_ms = its mean time per run).  Runs the probes several
  * times, writing the descriptors' outputs.  Synchronous.  Errors as for

@@ -16,6 +16,7 @@ struct lj_batch_plan {
     std::vector<lj_batch_desc> descs;
     std::vector<uint64_t> ws_off;    // per batch workspace offset
     std::vector<uint32_t> kpl;       // per batch keys per lane
+    std::vector<int> mode;           // per batch probe form (see uses_binned)
     std::vector<uint32_t> branch;    // per batch branch
     void* ws = nullptr;
     uint32_t branches = 1;
@@ -51,6 +52,7 @@ void default_tuning(lj_batch_tuning* t) {
     t->keys_per_lane[3] = 24;
     t->branches = 4;
     t->use_graph = 1;
+    t->binned_min_keys = 0;
     t->measured_ms = 0.f;
 }
 
@@ -74,12 +76,18 @@ int validate_descs(const lj_batch_desc* d, uint32_t k, int device) {
     return LJ_OK;
 }
 
-hipError_t enqueue_one(const lj_batch_desc& d, void* ws, uint32_t kpl, hipStream_t st) {
+int batch_mode(const lj_batch_tuning& t, uint64_t m) {
+    if (t.binned_min_keys == 0) return -1;
+    return m >= t.binned_min_keys ? 1 : 0;
+}
+
+hipError_t enqueue_one(const lj_batch_desc& d, void* ws, uint32_t kpl, int mode,
+                       hipStream_t st) {
     if (d.m == 0) return launch_set_u64(d.out_count_dev, 0, st);
     if (d.index->max_mult > 1) kpl = std::min<uint32_t>(kpl, kItemsDup);
     return launch_probe(d.index, d.s_keys_dev, d.m, d.out_pairs_dev,
                         d.out_pairs_dev ? d.out_capacity : 0, d.out_count_dev, ws, st, nullptr,
-                        nullptr, kpl);
+                        nullptr, kpl, mode);
 }
 
 }  // namespace lj
@@ -93,7 +101,7 @@ hipError_t enqueue_plan(lj_batch_plan* p, hipStream_t stream) {
     if (p->branches == 1) {
         for (size_t b = 0; b < k; ++b) {
             hipError_t e = lj::enqueue_one(p->descs[b], (char*)p->ws + p->ws_off[b], p->kpl[b],
-                                           stream);
+                                           p->mode[b], stream);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -102,7 +110,7 @@ hipError_t enqueue_plan(lj_batch_plan* p, hipStream_t stream) {
     for (uint32_t r = 0; r < p->branches && e == hipSuccess; ++r)
         e = hipStreamWaitEvent(p->streams[r], p->fork, 0);
     for (size_t b = 0; b < k && e == hipSuccess; ++b)
-        e = lj::enqueue_one(p->descs[b], (char*)p->ws + p->ws_off[b], p->kpl[b],
+        e = lj::enqueue_one(p->descs[b], (char*)p->ws + p->ws_off[b], p->kpl[b], p->mode[b],
                             p->streams[p->branch[b]]);
     for (uint32_t r = 0; r < p->branches && e == hipSuccess; ++r) {
         e = hipEventRecord(p->join[r], p->streams[r]);
@@ -137,7 +145,8 @@ int plan_create(const lj_batch_desc* descs, uint32_t k, const lj_batch_tuning* t
     for (uint32_t b = 0; b < k; ++b) {
         p->ws_off.push_back(off);
         p->kpl.push_back(t.keys_per_lane[lj::size_class(descs[b].m)]);
-        off = lj::align256(off + lj::ws_bytes(descs[b].index, descs[b].m));
+        p->mode.push_back(lj::batch_mode(t, descs[b].m));
+        off = lj::align256(off + lj::ws_bytes(descs[b].index, descs[b].m, p->mode[b]));
     }
     // Longest-processing-time assignment of batches to branches.
     std::vector<uint32_t> order(k);
@@ -232,8 +241,11 @@ int lj_batch_autotune(const lj_batch_desc* descs, uint32_t k, hipStream_t stream
                       lj_batch_tuning* tuning) {
     if (!tuning || !descs) return LJ_ERR_ARG;
     bool present[4] = {false, false, false, false};
-    for (uint32_t b = 0; b < k; ++b)
+    uint64_t max_m = 0;
+    for (uint32_t b = 0; b < k; ++b) {
         if (descs[b].m) present[lj::size_class(descs[b].m)] = true;
+        max_m = std::max(max_m, descs[b].m);
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         if (e0) (void)hipEventDestroy(e0);
@@ -270,6 +282,18 @@ int lj_batch_autotune(const lj_batch_desc* descs, uint32_t k, hipStream_t stream
         if (st != LJ_OK) break;
         lj_batch_tuning c = best;
         c.branches = br;
+        float ms = measure(c, &st);
+        if (st == LJ_OK && ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    // Binned probe from some batch size on (only sizes some batch reaches).
+    for (uint64_t bm : {~0ull, 1ull << 22, 1ull << 20, 1ull << 18}) {
+        if (st != LJ_OK) break;
+        if (bm != ~0ull && bm > max_m) continue;
+        lj_batch_tuning c = best;
+        c.binned_min_keys = bm;
         float ms = measure(c, &st);
         if (st == LJ_OK && ms < best_ms) {
             best_ms = ms;

@@ -14,8 +14,11 @@ int size_class(uint64_t m);
 void default_tuning(lj_batch_tuning* t);
 int validate_tuning(const lj_batch_tuning& t);
 int validate_descs(const lj_batch_desc* d, uint32_t k, int device);
-// Enqueue one batch (a fused probe, or zeroing the count of an empty batch)
-// with workspace `ws` of at least ws_bytes(d.index, d.m) bytes.
-hipError_t enqueue_one(const lj_batch_desc& d, void* ws, uint32_t kpl, hipStream_t st);
+// Probe form of a batch of m keys under tuning t (see uses_binned).
+int batch_mode(const lj_batch_tuning& t, uint64_t m);
+// Enqueue one batch (a probe, or zeroing the count of an empty batch) with
+// workspace `ws` of at least ws_bytes(d.index, d.m, mode) bytes.
+hipError_t enqueue_one(const lj_batch_desc& d, void* ws, uint32_t kpl, int mode,
+                       hipStream_t st);
 
 }  // namespace lj

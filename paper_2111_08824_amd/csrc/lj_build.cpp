@@ -179,8 +179,9 @@ int fit_rmi(const uint64_t* r, uint64_t n, uint32_t L, uint32_t flags, lj_index*
     }
     idx->max_mult = mm;
 
-    // Equi-depth key ranges of R for the binned probe.
-    if ((flags & LJ_PROBE_BINNED) && n > 0) {
+    // Equi-depth key ranges of R for the binned probe (built for every
+    // index, 61 KB, so that batched plans can choose the binned probe).
+    if (n > 0) {
         idx->fences.resize(kBins - 1);
         for (uint32_t i = 0; i + 1 < kBins; ++i)
             idx->fences[i] = r[((uint64_t)(i + 1) * n) / kBins];

@@ -150,12 +150,15 @@ inline BinnedWs binned_ws(uint64_t m) {
     L.total = a;
     return L;
 }
-inline bool uses_binned(const lj_index* idx, uint64_t m) {
-    return (idx->flags & LJ_PROBE_BINNED) && idx->n > 0 && m > 0;
+// Probe form: mode < 0 follows the index's LJ_PROBE_BINNED flag, 0 is the
+// direct probe, > 0 the binned probe (when R is not empty).
+inline bool uses_binned(const lj_index* idx, uint64_t m, int mode = -1) {
+    const bool want = mode < 0 ? (idx->flags & LJ_PROBE_BINNED) != 0 : mode > 0;
+    return want && idx->n > 0 && m > 0 && !idx->fences.empty();
 }
 // Workspace of one probe of m keys against idx.
-inline uint64_t ws_bytes(const lj_index* idx, uint64_t m) {
-    return uses_binned(idx, m) ? binned_ws(m).total : ws_bytes_direct(m);
+inline uint64_t ws_bytes(const lj_index* idx, uint64_t m, int mode = -1) {
+    return uses_binned(idx, m, mode) ? binned_ws(m).total : ws_bytes_direct(m);
 }
 
 // Everything the device needs to probe the tiles of one batch of outer keys
@@ -192,7 +195,8 @@ bool probe_kpl_supported(uint32_t kpl, bool dup);
 hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m,
                         lj_pair* out, uint64_t cap, uint64_t* count_dev,
                         void* ws, hipStream_t stream, hipEvent_t ev0,
-                        hipEvent_t ev1, uint32_t kpl = 0);  // kpl: direct probe only
+                        hipEvent_t ev1, uint32_t kpl = 0,  // kpl: direct probe only
+                        int mode = -1);                    // see uses_binned
 // Binned probe pieces (lj_partition.hip): the two partition passes of S
 // into the workspace laid out by binned_ws(m); out[p] = in[dest[p]] over m
 // elements of 4 bytes (8 with `wide`); the same with the number of pairs of

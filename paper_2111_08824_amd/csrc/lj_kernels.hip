@@ -674,8 +674,8 @@ hipError_t launch_probe_binned(const lj_index* idx, const uint64_t* s, uint64_t 
 
 hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m, lj_pair* out,
                         uint64_t cap, uint64_t* count_dev, void* ws, hipStream_t stream,
-                        hipEvent_t ev0, hipEvent_t ev1, uint32_t kpl) {
-    if (uses_binned(idx, m))
+                        hipEvent_t ev0, hipEvent_t ev1, uint32_t kpl, int mode) {
+    if (uses_binned(idx, m, mode))
         return launch_probe_binned(idx, s, m, out, cap, count_dev, ws, stream, ev0, ev1);
     const uint32_t kind = job_kind(idx);
     if (kpl == 0) kpl = (kind & kJobDup) ? kItemsDup : kItemsUnique;

@@ -162,7 +162,7 @@ hipError_t lj_server::enqueue_batch(Slot* s) {
         d.out_count_dev = (uint64_t*)(base + r->cnt_off);
         if (e == hipSuccess)
             e = lj::enqueue_one(d, base + r->ws_off, cfg.keys_per_lane[lj::size_class(r->m)],
-                                s->stream);
+                                -1, s->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(&s->counts_host[i], base + r->cnt_off, 8, hipMemcpyDeviceToHost,
                                s->stream);

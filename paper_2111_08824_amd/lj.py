@@ -82,12 +82,14 @@ class lj_batch_tuning(ctypes.Structure):
         ("keys_per_lane", ctypes.c_uint32 * 4),
         ("branches", ctypes.c_uint32),
         ("use_graph", ctypes.c_uint32),
+        ("binned_min_keys", ctypes.c_uint64),
         ("measured_ms", ctypes.c_float),
     ]
 
     def as_dict(self):
         return {"keys_per_lane": list(self.keys_per_lane), "branches": self.branches,
-                "use_graph": self.use_graph, "measured_ms": self.measured_ms}
+                "use_graph": self.use_graph, "binned_min_keys": self.binned_min_keys,
+                "measured_ms": self.measured_ms}
 
 
 class lj_server_config(ctypes.Structure):

@@ -41,14 +41,17 @@ def _check(items):
 
 
 @pytest.mark.parametrize("use_graph", [0, 1])
-def test_plan_matches_oracle_on_every_replay(use_graph):
+@pytest.mark.parametrize("binned_min_keys", [0, 1, 5000])
+def test_plan_matches_oracle_on_every_replay(use_graph, binned_min_keys):
     import torch
     items = _mixed_batches()
     t = lj.lj_batch_default_tuning()
     t.use_graph = use_graph
+    t.binned_min_keys = binned_min_keys  # index flags / every batch binned / large ones
     plan = lj.BatchPlan([(ix, s, out, cnt) for _, _, ix, s, out, cnt in items], t)
     for rep in range(3):
-        print(f"[batches] replay {rep} graph={use_graph}", flush=True)
+        print(f"[batches] replay {rep} graph={use_graph} binned_min_keys={binned_min_keys}",
+              flush=True)
         for *_, out, cnt in items:  # eager work between replays
             out.fill_(-1)
             cnt.fill_(-7)

@@ -81,6 +81,14 @@ def test_workspace_sizes():
     assert lj.lj_probe_workspace_bytes(binned, 0) == lj.lj_probe_workspace_bytes(direct, 0)
 
 
+def test_default_batch_tuning_layout():
+    # Filled by the library: a layout mismatch with lj.h shows as wrong fields.
+    t = lj.lj_batch_default_tuning()
+    assert list(t.keys_per_lane) == [4, 8, 16, 24]
+    assert (t.branches, t.use_graph, t.binned_min_keys, t.measured_ms) == (4, 1, 0, 0.0)
+    assert ctypes.sizeof(lj.lj_batch_tuning) == 40
+
+
 def test_probe_of_host_only_index_is_rejected():
     ix = lj.lj_build_rmi_host_only(np.arange(10, dtype=np.uint64), 2)
     cnt = ctypes.c_uint64()
