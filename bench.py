@@ -193,7 +193,9 @@ def bench_serving(args) -> None:
     plain per-request probe, run through the serving loop configured as the
     plain per-request probe (one stream, one request per launch) and as the
     continuously batching server (8 streams, up to 16 requests and 2^22 keys
-    per batch)."""
+    per batch).  --request-buffers device keeps request keys and pairs in
+    HBM (lj_server_submit_device: no PCIe copies) and adds a server
+    configuration that probes requests of 2^20 keys or more binned."""
     import threading
     import queue as pyqueue
 
@@ -220,15 +222,23 @@ def bench_serving(args) -> None:
         return out
 
     # Outer-key pools in pinned host memory (requests are views into them) and
-    # a ring of pinned output buffers.
+    # a ring of pinned output buffers; or both in device memory.
+    on_device = args.request_buffers == "device"
     pool = len(ws[0].S)
-    pin_s = torch.empty((len(ws), pool), dtype=torch.int64, pin_memory=True)
-    s_np = pin_s.numpy().view(np.uint64)
-    for i, w in enumerate(ws):
-        s_np[i] = w.S
     nbuf = 32
-    pin_o = torch.empty((nbuf, max_m, 2), dtype=torch.int32, pin_memory=True)
-    o_np = pin_o.numpy().view(np.uint32)
+    if on_device:
+        s_dev = torch.empty((len(ws), pool), dtype=torch.int64, device="cuda")
+        for i, w in enumerate(ws):
+            s_dev[i] = lj.to_device_keys(w.S)
+        o_dev = torch.empty((nbuf, max_m, 2), dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+    else:
+        pin_s = torch.empty((len(ws), pool), dtype=torch.int64, pin_memory=True)
+        s_np = pin_s.numpy().view(np.uint64)
+        for i, w in enumerate(ws):
+            s_np[i] = w.S
+        pin_o = torch.empty((nbuf, max_m, 2), dtype=torch.int32, pin_memory=True)
+        o_np = pin_o.numpy().view(np.uint32)
 
     def run(cfg, reqs, rate):
         """Submit reqs (Poisson arrivals at `rate` per second, or all at once
@@ -259,7 +269,10 @@ def bench_serving(args) -> None:
                 if d > 0:
                     time.sleep(d)
             b = free.get()
-            t = srv.submit(i, s_np[i, a:a + m], o_np[b, :m])
+            if on_device:
+                t = srv.submit_device(i, s_dev[i, a:a + m], o_dev[b, :m])
+            else:
+                t = srv.submit(i, s_np[i, a:a + m], o_np[b, :m])
             tickets.put((t, b, m))
         th.join()
         wall = time.perf_counter() - start
@@ -270,23 +283,33 @@ def bench_serving(args) -> None:
     plain = lj.lj_server_default_config(24 << 30)
     plain.slots, plain.max_batch_requests = 1, 1
     served = lj.lj_server_default_config(24 << 30)
+    configs = [("plain_per_request", plain), ("served", served)]
+    if on_device:
+        served_binned = lj.lj_server_default_config(24 << 30)
+        served_binned.binned_min_keys = 1 << 20
+        configs.append(("served_binned", served_binned))
 
     warm = make_requests(64)
-    run(plain, warm, None)
-    run(served, warm, None)
+    for _, cfg in configs:
+        run(cfg, warm, None)
     sat_reqs = make_requests(nreq)
     keys_sat = sum(m for _, _, m in sat_reqs)
-    w_plain, _, _ = run(plain, sat_reqs, None)
-    w_served, _, st_sat = run(served, sat_reqs, None)
+    sat = {}
+    for name, cfg in configs:
+        wall, _, st = run(cfg, sat_reqs, None)
+        sat[name] = (wall, st)
+        print(f"[bench] saturation {name}: {len(sat_reqs) / wall:.1f} req/s, "
+              f"{keys_sat / wall:.3e} probes/s", file=sys.stderr, flush=True)
+    w_plain = sat["plain_per_request"][0]
+    best = min((n for n, _ in configs if n != "plain_per_request"), key=lambda n: sat[n][0])
+    w_served, st_sat = sat[best]
     sat_rate = len(sat_reqs) / w_plain
-    print(f"[bench] saturation: plain {sat_rate:.1f} req/s, served "
-          f"{len(sat_reqs) / w_served:.1f} req/s", file=sys.stderr, flush=True)
     loads = {}
     for load in (0.5, 0.8):
         reqs = make_requests(nreq)
         keys = sum(m for _, _, m in reqs)
         row = {}
-        for name, cfg in (("plain_per_request", plain), ("served", served)):
+        for name, cfg in configs:
             wall, lat, st = run(cfg, reqs, load * sat_rate)
             row[name] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
                          "p99_ms": round(float(np.percentile(lat, 99)), 3),
@@ -300,9 +323,9 @@ def bench_serving(args) -> None:
         "ms_per_step": round(w_served * 1e3 / len(sat_reqs), 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "serving-8x50M", "indexes": 8, "inner_keys_each": 50_000_000,
-                   "request_keys": "log-uniform 256..4194304", "requests_per_load": nreq},
-        "saturation": {"plain_per_request_probes_per_s": keys_sat / w_plain,
-                       "served_probes_per_s": keys_sat / w_served,
+                   "request_keys": "log-uniform 256..4194304", "requests_per_load": nreq,
+                   "request_buffers": args.request_buffers, "server": best},
+        "saturation": {**{f"{n}_probes_per_s": keys_sat / sat[n][0] for n, _ in configs},
                        "served_max_batch": int(st_sat.max_batch_size)},
         "loads": loads,
         "roofline": None, "cpu_baseline": None,
@@ -324,6 +347,9 @@ def main():
                     help="outer keys in the timed oracle sample (0 = skip)")
     ap.add_argument("--requests", type=int, default=1000,
                     help="requests per load level in the serving workload")
+    ap.add_argument("--request-buffers", choices=["host", "device"], default="host",
+                    help="serving workload: request keys and pairs in pinned host memory "
+                         "(copied over PCIe) or already in device memory")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the steps, run a plain device copy of this many MiB "
                          "(reference point for HBM byte counters)")

@@ -259,6 +259,9 @@ typedef struct {
     uint64_t max_batch_keys;      /* outer keys per batch (a larger single request
                                      still forms a batch alone), >= 1 */
     uint32_t keys_per_lane[4];    /* tile shape per size class, as in lj_batch_tuning */
+    uint64_t binned_min_keys;     /* requests of at least this many keys use the binned
+                                     probe, smaller ones the direct probe; 0 keeps each
+                                     index's own choice (LJ_PROBE_BINNED) */
 } lj_server_config;
 
 typedef struct lj_server lj_server;
@@ -282,7 +285,7 @@ typedef struct {
 } lj_server_stats;
 
 /* Fill *config with defaults for a budget: 8 slots, 16 requests and 2^22
- * keys per batch, keys per lane 4/8/16/24. */
+ * keys per batch, keys per lane 4/8/16/24, binned_min_keys 0. */
 void lj_server_default_config(lj_server_config* config, uint64_t budget_bytes);
 
 /*
@@ -304,6 +307,19 @@ int lj_server_create(lj_index* const* indexes, uint32_t n_indexes,
 int lj_server_submit(lj_server* server, uint32_t index_id, const uint64_t* s_keys_host,
                      uint64_t m, lj_pair* out_pairs_host, uint64_t out_capacity,
                      uint64_t* out_ticket);
+
+/*
+ * Submit a request whose keys and pairs already live in device memory of
+ * the server's GPU (for producers and consumers on the GPU): no copies are
+ * made; the probe reads s_keys_dev and writes up to out_capacity pairs to
+ * out_pairs_dev directly, and only its workspace and count word come from
+ * the arena.  Both buffers must stay valid and untouched until the request
+ * completes.  Same tickets, results and errors as lj_server_submit.
+ */
+int lj_server_submit_device(lj_server* server, uint32_t index_id,
+                            const uint64_t* s_keys_dev, uint64_t m,
+                            lj_pair* out_pairs_dev, uint64_t out_capacity,
+                            uint64_t* out_ticket);
 
 /*
  * Wait until a request completes (timeout_ms < 0: no limit) and fetch its

@@ -68,9 +68,11 @@ class Arena {
 struct Request {
     uint64_t ticket = 0;
     uint32_t index_id = 0;
-    const uint64_t* s_host = nullptr;
+    bool on_device = false;  // keys and pairs in device memory (no copies)
+    int mode = -1;           // probe form (see uses_binned)
+    const uint64_t* s_host = nullptr;  // the caller's keys (device memory when on_device)
     uint64_t m = 0;
-    lj_pair* out_host = nullptr;
+    lj_pair* out_host = nullptr;  // the caller's pairs (device memory when on_device)
     uint64_t cap = 0;
     uint64_t devcap = 0;  // pairs the device buffer holds
     uint64_t bytes = 0;   // arena footprint
@@ -118,15 +120,18 @@ struct lj_server {
 
 namespace {
 
+// Arena bytes of a request: keys, pairs (host requests only), workspace and
+// the count word.
 uint64_t footprint(const lj_index* idx, uint64_t m, uint64_t cap, Request* r) {
-    uint64_t devcap = std::min<uint64_t>(cap, m * std::max<uint64_t>(idx->max_mult, 1));
+    const bool dev = r->on_device;
+    uint64_t devcap = dev ? cap : std::min<uint64_t>(cap, m * std::max<uint64_t>(idx->max_mult, 1));
     uint64_t off = 0;
     uint64_t s_off = off;
-    off = lj::align256(off + 8 * m);
+    off = lj::align256(off + (dev ? 0 : 8 * m));
     uint64_t out_off = off;
-    off = lj::align256(off + 8 * devcap);
+    off = lj::align256(off + (dev ? 0 : 8 * devcap));
     uint64_t ws_off = off;
-    off = lj::align256(off + lj::ws_bytes(idx, m));
+    off = lj::align256(off + lj::ws_bytes(idx, m, r->mode));
     uint64_t cnt_off = off;
     off = lj::align256(off + 8);
     if (r) {
@@ -142,27 +147,29 @@ uint64_t footprint(const lj_index* idx, uint64_t m, uint64_t cap, Request* r) {
 
 }  // namespace
 
-// Per request, in batch order: keys in, fused probe, count out, then an
-// event, so that the completion thread can return each request as soon as
-// its own work is done.
+// Per request, in batch order: keys in (host requests), probe, count out,
+// then an event, so that the completion thread can return each request as
+// soon as its own work is done.
 hipError_t lj_server::enqueue_batch(Slot* s) {
     hipError_t e = hipSuccess;
     for (size_t i = 0; i < s->batch.size() && e == hipSuccess; ++i) {
         Request* r = s->batch[i];
         char* base = arena_base + r->off;
-        if (r->m)
+        if (r->m && !r->on_device)  // device requests bring their keys in place
             e = hipMemcpyAsync(base + r->s_off, r->s_host, 8 * r->m, hipMemcpyHostToDevice,
                                s->stream);
         lj_batch_desc d;
         d.index = indexes[r->index_id];
-        d.s_keys_dev = (const uint64_t*)(base + r->s_off);
+        d.s_keys_dev = r->on_device ? r->s_host : (const uint64_t*)(base + r->s_off);
         d.m = r->m;
-        d.out_pairs_dev = r->devcap ? (lj_pair*)(base + r->out_off) : nullptr;
+        d.out_pairs_dev = !r->devcap ? nullptr
+                          : r->on_device ? r->out_host
+                                         : (lj_pair*)(base + r->out_off);
         d.out_capacity = r->devcap;
         d.out_count_dev = (uint64_t*)(base + r->cnt_off);
         if (e == hipSuccess)
             e = lj::enqueue_one(d, base + r->ws_off, cfg.keys_per_lane[lj::size_class(r->m)],
-                                -1, s->stream);
+                                r->mode, s->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(&s->counts_host[i], base + r->cnt_off, 8, hipMemcpyDeviceToHost,
                                s->stream);
@@ -236,7 +243,7 @@ void lj_server::slot_loop(Slot* s) {
             Request* r = batch[i];
             bool ok = r->res.status == LJ_OK && hipEventSynchronize(s->events[i]) == hipSuccess;
             uint64_t count = ok ? s->counts_host[i] : ~0ull;
-            if (ok && count != ~0ull) {
+            if (ok && count != ~0ull && !r->on_device) {
                 uint64_t n = std::min(count, std::min(r->cap, r->devcap));
                 if (n)
                     ok = hipMemcpyAsync(r->out_host, arena_base + r->off + r->out_off,
@@ -281,6 +288,7 @@ void lj_server_default_config(lj_server_config* c, uint64_t budget_bytes) {
     c->keys_per_lane[1] = 8;
     c->keys_per_lane[2] = 16;
     c->keys_per_lane[3] = 24;
+    c->binned_min_keys = 0;
 }
 
 int lj_server_create(lj_index* const* indexes, uint32_t n, const lj_server_config* cfg,
@@ -343,14 +351,21 @@ int lj_server_create(lj_index* const* indexes, uint32_t n, const lj_server_confi
     return LJ_OK;
 }
 
-int lj_server_submit(lj_server* sv, uint32_t index_id, const uint64_t* s_host, uint64_t m,
-                     lj_pair* out_host, uint64_t cap, uint64_t* ticket) {
+}  // extern "C"
+
+namespace {
+
+int submit(lj_server* sv, uint32_t index_id, const uint64_t* s_host, uint64_t m,
+           lj_pair* out_host, uint64_t cap, bool on_device, uint64_t* ticket) {
     if (!sv || !ticket || index_id >= sv->indexes.size()) return LJ_ERR_ARG;
     if ((m && !s_host) || (cap && !out_host)) return LJ_ERR_ARG;
     if (m >= (1ull << 32)) return LJ_ERR_TOO_LARGE;
     Request* r = new (std::nothrow) Request();
     if (!r) return LJ_ERR_OOM;
     r->index_id = index_id;
+    r->on_device = on_device;
+    const uint64_t bmin = sv->cfg.binned_min_keys;
+    r->mode = bmin == 0 ? -1 : (m >= bmin ? 1 : 0);
     r->s_host = s_host;
     r->m = m;
     r->out_host = out_host;
@@ -374,6 +389,20 @@ int lj_server_submit(lj_server* sv, uint32_t index_id, const uint64_t* s_host, u
     *ticket = r->ticket;
     sv->cv_sched.notify_all();
     return LJ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lj_server_submit(lj_server* sv, uint32_t index_id, const uint64_t* s_host, uint64_t m,
+                     lj_pair* out_host, uint64_t cap, uint64_t* ticket) {
+    return submit(sv, index_id, s_host, m, out_host, cap, false, ticket);
+}
+
+int lj_server_submit_device(lj_server* sv, uint32_t index_id, const uint64_t* s_dev,
+                            uint64_t m, lj_pair* out_dev, uint64_t cap, uint64_t* ticket) {
+    return submit(sv, index_id, s_dev, m, out_dev, cap, true, ticket);
 }
 
 int lj_server_wait(lj_server* sv, uint64_t ticket, int64_t timeout_ms, lj_request_result* res) {

@@ -38,8 +38,8 @@ EXPORTED = (
     "lj_predict_windows_host", "lj_build_rmi_host_only", "lj_probe_set_timing_events",
     "lj_bench_random_gather", "lj_strerror", "lj_batch_default_tuning",
     "lj_batch_plan_create", "lj_batch_plan_run", "lj_batch_plan_destroy", "lj_batch_autotune",
-    "lj_server_default_config", "lj_server_create", "lj_server_submit", "lj_server_wait",
-    "lj_server_get_stats", "lj_server_destroy",
+    "lj_server_default_config", "lj_server_create", "lj_server_submit",
+    "lj_server_submit_device", "lj_server_wait", "lj_server_get_stats", "lj_server_destroy",
 )
 
 
@@ -99,6 +99,7 @@ class lj_server_config(ctypes.Structure):
         ("max_batch_requests", ctypes.c_uint32),
         ("max_batch_keys", ctypes.c_uint64),
         ("keys_per_lane", ctypes.c_uint32 * 4),
+        ("binned_min_keys", ctypes.c_uint64),
     ]
 
 
@@ -165,6 +166,7 @@ def lib() -> ctypes.CDLL:
         L.lj_server_create.argtypes = [ctypes.POINTER(vp), u32, ctypes.POINTER(lj_server_config),
                                        ctypes.POINTER(vp)]
         L.lj_server_submit.argtypes = [vp, u32, vp, u64, vp, u64, ctypes.POINTER(u64)]
+        L.lj_server_submit_device.argtypes = [vp, u32, vp, u64, vp, u64, ctypes.POINTER(u64)]
         L.lj_server_wait.argtypes = [vp, u64, ctypes.c_int64, ctypes.POINTER(lj_request_result)]
         L.lj_server_get_stats.argtypes = [vp, ctypes.POINTER(lj_server_stats)]
         L.lj_server_destroy.argtypes = [vp]
@@ -176,7 +178,8 @@ def lib() -> ctypes.CDLL:
                   "lj_predict_windows", "lj_predict_windows_host",
                   "lj_probe_set_timing_events", "lj_bench_random_gather",
                   "lj_batch_plan_create", "lj_batch_plan_run", "lj_batch_autotune",
-                  "lj_server_create", "lj_server_submit", "lj_server_wait",
+                  "lj_server_create", "lj_server_submit", "lj_server_submit_device",
+                  "lj_server_wait",
                   "lj_server_get_stats"):
             getattr(L, f).restype = i32
         _lib = L
@@ -411,6 +414,19 @@ class Server:
                                       len(s_keys_host),
                                       out_pairs_host.ctypes.data if cap else None, cap,
                                       ctypes.byref(t)), "lj_server_submit")
+        return t.value
+
+    def submit_device(self, index_id: int, s_keys_dev, out_pairs_dev) -> int:
+        """Device-resident request: s_keys_dev an int64 CUDA tensor of keys,
+        out_pairs_dev an (cap, 2) int32 CUDA tensor or None; both must stay
+        alive and untouched until wait() returns for the ticket."""
+        m = s_keys_dev.numel()
+        cap = 0 if out_pairs_dev is None else out_pairs_dev.shape[0]
+        t = ctypes.c_uint64()
+        _check(lib().lj_server_submit_device(self.handle, index_id,
+                                             _dev_ptr(s_keys_dev) if m else None, m,
+                                             _dev_ptr(out_pairs_dev) if cap else None, cap,
+                                             ctypes.byref(t)), "lj_server_submit_device")
         return t.value
 
     def wait(self, ticket: int, timeout_ms: int = -1) -> lj_request_result:

@@ -120,3 +120,39 @@ def test_oversize_request_and_bad_arguments():
     r = srv.wait(t, 60_000)
     assert r.status == lj.LJ_OK and r.count == len(oracle.sort_merge_join(ws[0].R, small))
     srv.close()
+
+
+@pytest.mark.parametrize("binned_min_keys", [0, 1, 50_000])
+def test_device_requests_mixed_with_host_requests(binned_min_keys):
+    """Device-resident requests (no copies) interleaved with host requests,
+    with the binned probe for none / all / large requests: every result
+    equals the oracle's and the request's result alone."""
+    import torch
+    ws, ixs = _indexes()
+    reqs = _requests(ws, 60, seed=23 + binned_min_keys % 7)
+    cfg = lj.lj_server_default_config(1 << 28)
+    cfg.slots = 4
+    cfg.binned_min_keys = binned_min_keys
+    srv = lj.Server(ixs, cfg)
+    tickets, dev_bufs = [], []
+    for q, (i, S, want, cap, out) in enumerate(reqs):
+        if q % 2:
+            s_dev = lj.to_device_keys(S)
+            o_dev = torch.full((max(cap, 1), 2), -1, dtype=torch.int32, device="cuda")
+            dev_bufs.append((s_dev, o_dev))
+            tickets.append(srv.submit_device(i, s_dev, o_dev if cap else None))
+        else:
+            dev_bufs.append(None)
+            tickets.append(srv.submit(i, S, out if cap else None))
+    print(f"[server] device requests binned_min_keys={binned_min_keys}", flush=True)
+    for q, (i, S, want, cap, out) in enumerate(reqs):
+        r = srv.wait(tickets[q], 60_000)
+        assert r.count == len(want), (q, r.count, len(want))
+        assert r.status == (lj.LJ_OK if cap >= len(want) else lj.LJ_ERR_CAPACITY)
+        if dev_bufs[q] is not None:
+            got = dev_bufs[q][1][:min(cap, len(want))].cpu().numpy().view(np.uint32)
+        else:
+            got = out[:min(cap, len(want))]
+        assert np.array_equal(got, want[:cap])
+    assert srv.stats.requests_done == len(reqs)
+    srv.close()
