@@ -45,11 +45,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str, binned: bool):
+def load_traffic(workload: str, binned: bool, gapped: bool = False):
     """HBM bytes per launch of the timed kernel from the committed rocprofv3
     counter summary, or None when absent or taken on a different kernel
     source."""
-    kind = "probe_binned" if binned else "probe"
+    kind = ("probe_binned" if binned else "probe") + ("_gapped" if gapped else "")
     path = os.path.join(ROOT, "profiles", f"{kind}_{workload}_hbm_counters.md")
     if not os.path.exists(path):
         return None
@@ -78,13 +78,15 @@ def make_workload(name: str):
 
 
 def algorithmic_bytes(pairs_dev, count: int, m: int, out_per_key: float = 0.0,
-                      out_per_pair: float = 8.0) -> float:
+                      out_per_pair: float = 8.0, slot_bytes: int = 8) -> float:
     """Compulsory HBM bytes of one launch of the probe kernel: 8 B per outer
-    key read, one 64 B sector of R per outer key (its insertion point, or
-    every sector its match run spans), and its output: 8 B per emitted pair
-    (fused probe), or out_per_key bytes of per-key result (search kernel of
-    the binned probe).  Computed from the emitted pairs: a key with matches
-    owns one contiguous run of r indices."""
+    key read, one 64 B sector of the searched array per outer key (its
+    insertion point, or every sector its match run spans), and its output:
+    8 B per emitted pair (fused probe), or out_per_key bytes of per-key
+    result (search kernel of the binned probe).  The searched array is R
+    (8 B per key) or a gapped RMI's slots (slot_bytes = 16).  Computed from
+    the emitted pairs: a key with matches owns one contiguous run of r
+    indices, and of slots."""
     import torch
     sectors = float(m)
     if count:
@@ -94,7 +96,8 @@ def algorithmic_bytes(pairs_dev, count: int, m: int, out_per_key: float = 0.0,
         new[1:] = s[1:] != s[:-1]
         last = torch.ones(count, dtype=torch.bool, device=p.device)
         last[:-1] = new[1:]
-        span = (r[last] // 8 - r[new] // 8 + 1).sum().item()
+        per = 64 // slot_bytes
+        span = (r[last] // per - r[new] // per + 1).sum().item()
         sectors += float(span) - float(new.sum().item())
     return 8.0 * m + 64.0 * sectors + out_per_key * m + out_per_pair * count
 
@@ -343,6 +346,10 @@ def main():
                     help="last-mile search inside the error bounds")
     ap.add_argument("--probe", choices=["direct", "binned"], default="binned",
                     help="probe S in its own order, or partitioned by key range first")
+    ap.add_argument("--index", choices=["rmi", "gapped"], default="rmi",
+                    help="plain RMI over R, or gapped RMI (model-based insertion)")
+    ap.add_argument("--slots-per-key", type=int, default=4,
+                    help="gapped RMI: slots of the gapped arrays per key of R")
     ap.add_argument("--cpu-sample", type=int, default=120_000_000,
                     help="outer keys in the timed oracle sample (0 = skip)")
     ap.add_argument("--requests", type=int, default=1000,
@@ -379,15 +386,22 @@ def main():
     if binned:
         flags |= lj.LJ_PROBE_BINNED
     stream = torch.cuda.current_stream()
-    ix = lj.lj_build_rmi(w.R, w.leaves, flags, stream)
+    gapped = args.index == "gapped"
+    t0 = time.perf_counter()
+    if gapped:
+        ix = lj.lj_build_gapped_rmi(w.R, w.leaves, args.slots_per_key, flags, stream)
+    else:
+        ix = lj.lj_build_rmi(w.R, w.leaves, flags, stream)
+    build_s = time.perf_counter() - t0
     st = ix.stats
     s_dev = lj.to_device_keys(w.S)
     m = len(w.S)
     cap = m * int(st.max_mult)
     out = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
-    print(f"[bench] index built: mean window {st.mean_window:.1f}, max window "
-          f"{st.max_window}, nonempty leaves {st.nonempty_leaves}", file=sys.stderr, flush=True)
+    print(f"[bench] index built in {build_s:.1f} s: mean window {st.mean_window:.1f}, max "
+          f"window {st.max_window}, nonempty leaves {st.nonempty_leaves}, device bytes "
+          f"{st.device_bytes}", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         status, count = lj.lj_probe_join(ix, s_dev, out, stream)
@@ -423,14 +437,16 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    slot_bytes = 16 if gapped else 8
     if binned:  # search kernel: keys in, one 4-byte (8 with duplicates) result out
-        alg = algorithmic_bytes(out, int(count), m, 4.0 if st.max_mult <= 1 else 8.0, 0.0)
+        alg = algorithmic_bytes(out, int(count), m, 4.0 if st.max_mult <= 1 else 8.0, 0.0,
+                                slot_bytes)
     else:
-        alg = algorithmic_bytes(out, int(count), m)
+        alg = algorithmic_bytes(out, int(count), m, slot_bytes=slot_bytes)
     achieved = alg / (kern_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": load_traffic(w.name, binned),
+            "traffic": load_traffic(w.name, binned, gapped),
             "algorithmic_bytes_per_launch": alg,
             "kernel": "probe_binned_kernel" if binned else "probe_join_kernel",
             "kernel_ms": round(kern_ms, 4)}
@@ -451,7 +467,11 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": w.name, "n": len(w.R), "m": m, "leaves": w.leaves,
-                   "leaf_model": args.leaf, "search": args.search, "probe": args.probe,
+                   "leaf_model": args.leaf,
+                   "search": "gapped-exponential" if gapped else args.search,
+                   "probe": args.probe,
+                   "index": args.index,
+                   "slots_per_key": args.slots_per_key if gapped else None,
                    "pairs": int(count),
                    "mean_window": round(st.mean_window, 2), "max_window": int(st.max_window)},
         "roofline": roof,

@@ -101,6 +101,31 @@ enum {
 int lj_build_rmi(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves,
                  uint32_t flags, hipStream_t stream, lj_index** out_index);
 
+/*
+ * Build a gapped RMI (Section III-A, "Gapped RMI"): the same two-level RMI,
+ * then model-based insertion of R, in order, into gapped arrays of
+ * slots_per_key * n slots (a little more when predictions run past the
+ * end): key i goes to its predicted slot, or, when that slot is taken, to
+ * the slot right after key i - 1.  Keys, their payloads (the position in R)
+ * and the gap bitmap share one 16-byte slot; a gap holds the next key of R.
+ * A probe predicts the slot and searches exponentially forward from it
+ * (Section III-A, "GRMI Lookup"), bounded by the leaf's largest insertion
+ * drift; every entry point that takes an index (probes, plans, the server,
+ * LJ_PROBE_BINNED) works on it and emits the same pairs as for a plain RMI.
+ *
+ *   slots_per_key  1..16; the evaluation's setting of 4 gaps per key is
+ *                  read as 4 slots per key (the hash baselines matched to
+ *                  it run at load factor 25%).  Device memory: 16 bytes per
+ *                  slot, on top of R and the leaf table.
+ *
+ * Other arguments and errors as lj_build_rmi; LJ_ERR_ARG also for
+ * slots_per_key outside 1..16; LJ_ERR_TOO_LARGE also when the slot count
+ * reaches 2^32.
+ */
+int lj_build_gapped_rmi(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves,
+                        uint32_t slots_per_key, uint32_t flags, hipStream_t stream,
+                        lj_index** out_index);
+
 /* Release an index and its device memory.  NULL is ignored.  The caller
  * must ensure no probe of this index is still running on any stream. */
 void lj_free_index(lj_index* index);
@@ -344,11 +369,15 @@ typedef struct {
     uint32_t nonempty_leaves; /* leaves with at least one key */
     uint32_t max_leaf_keys;   /* keys in the largest leaf */
     uint64_t max_mult;        /* longest run of equal keys in R */
-    double mean_window;       /* mean search-window length over the keys of R */
+    double mean_window;       /* mean search-window length over the keys of R
+                                 (in slots for a gapped RMI) */
     uint64_t max_window;      /* largest search window of any leaf */
     uint64_t device_bytes;    /* device memory held (R + leaf table) */
     double root_a0, root_b0;  /* root model parameters */
     uint64_t root_kmin;       /* root model key origin (R[0]) */
+    uint32_t slots_per_key;   /* gapped RMI: slots per key of R (0: plain RMI) */
+    uint32_t pad;
+    uint64_t nslots;          /* gapped RMI: slots of the gapped arrays */
 } lj_index_stats;
 
 int lj_index_get_stats(const lj_index* index, lj_index_stats* out);
@@ -356,7 +385,10 @@ int lj_index_get_stats(const lj_index* index, lj_index_stats* out);
 /*
  * Device self-check: a GPU kernel routes and predicts every key of R with
  * the device arithmetic and counts keys whose own position falls outside
- * their search window (0 means the host-built bounds hold on the device).
+ * their search window (0 means the host-built bounds hold on the device);
+ * for a gapped RMI, every key slot whose key differs from R at its payload
+ * position or lies outside its slot window, plus the difference between
+ * the number of key slots and n.
  * Synchronous.  Errors: LJ_ERR_ARG, LJ_ERR_DEVICE, LJ_ERR_OOM.
  */
 int lj_self_check(const lj_index* index, uint64_t* out_violations_host,
@@ -366,7 +398,7 @@ int lj_self_check(const lj_index* index, uint64_t* out_violations_host,
  * Window diagnostics: for each of m keys (device memory), the leaf chosen by
  * the root, the predicted absolute position (-1 for an empty leaf) and the
  * absolute search window [lo, hi] the probe searches (lo > hi = empty
- * window).  Used by tests and for model-quality statistics; not part of the
+ * window); for a gapped RMI the predicted slot and the slot window.  Used by tests and for model-quality statistics; not part of the
  * join.  Any output pointer may be NULL.  Asynchronous on `stream`.
  */
 int lj_predict_windows(const lj_index* index, const uint64_t* keys_dev,
@@ -393,6 +425,24 @@ int lj_predict_windows_host(const lj_index* index, const uint64_t* keys_host,
 int lj_build_rmi_host_only(const uint64_t* r_keys_host, uint64_t n,
                            uint32_t leaves, uint32_t flags,
                            lj_index** out_index);
+
+/* Host-only build of a gapped RMI (arguments as lj_build_gapped_rmi); its
+ * slot arrays can be read with lj_gapped_slots_host. */
+int lj_build_gapped_rmi_host_only(const uint64_t* r_keys_host, uint64_t n,
+                                  uint32_t leaves, uint32_t slots_per_key,
+                                  uint32_t flags, lj_index** out_index);
+
+/*
+ * Copy the slot arrays of a host-only gapped RMI: for slot j < capacity,
+ * keys_host[j] (the key, or for a gap the next key of R) and ridx_host[j]
+ * (the key's position in R, or UINT32_MAX for a gap); *nslots_out receives
+ * the number of slots.  Errors: LJ_ERR_ARG (not a host-only gapped index),
+ * LJ_ERR_CAPACITY (capacity below the slot count; the first slots are
+ * copied).
+ */
+int lj_gapped_slots_host(const lj_index* index, uint64_t* keys_host,
+                         uint32_t* ridx_host, uint64_t capacity,
+                         uint64_t* nslots_out);
 
 /*
  * Timing hook for benchmarks: the next lj_probe_join or lj_probe_join_async

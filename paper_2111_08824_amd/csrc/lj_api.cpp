@@ -3,6 +3,7 @@
 // cache and the synchronous count readback.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <unordered_map>
@@ -14,6 +15,7 @@ namespace {
 constexpr uint64_t kMaxN = 1ull << 31;
 constexpr uint64_t kMaxM = 1ull << 32;
 constexpr uint32_t kMaxLeaves = 1u << 26;
+constexpr uint32_t kMaxSlotsPerKey = 16;  // gapped RMI: slots per key of R
 
 thread_local hipEvent_t t_ev_start = nullptr;
 thread_local hipEvent_t t_ev_stop = nullptr;
@@ -56,8 +58,10 @@ int validate_build(const uint64_t* r, uint64_t n, uint32_t leaves, uint32_t flag
     return LJ_OK;
 }
 
+// gap_factor 0: plain RMI; otherwise a gapped RMI with that many slots per
+// key of R.
 int build_common(const uint64_t* r, uint64_t n, uint32_t leaves, uint32_t flags,
-                 lj_index** out) {
+                 uint32_t gap_factor, lj_index** out) {
     if (!out) return LJ_ERR_ARG;
     *out = nullptr;
     int st = validate_build(r, n, leaves, flags);
@@ -66,6 +70,7 @@ int build_common(const uint64_t* r, uint64_t n, uint32_t leaves, uint32_t flags,
     if (!idx) return LJ_ERR_OOM;
     try {
         st = lj::fit_rmi(r, n, leaves, flags, idx);
+        if (st == LJ_OK && gap_factor) st = lj::fit_gapped(r, gap_factor, idx);
     } catch (const std::bad_alloc&) {
         st = LJ_ERR_OOM;
     }
@@ -77,20 +82,50 @@ int build_common(const uint64_t* r, uint64_t n, uint32_t leaves, uint32_t flags,
     return LJ_OK;
 }
 
+int build_device(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves, uint32_t flags,
+                 uint32_t gap_factor, hipStream_t stream, lj_index** out_index);
+
 }  // namespace
 
 extern "C" {
 
 int lj_build_rmi_host_only(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves,
                            uint32_t flags, lj_index** out_index) {
-    int st = build_common(r_keys_host, n, leaves, flags, out_index);
+    int st = build_common(r_keys_host, n, leaves, flags, 0, out_index);
+    if (st == LJ_OK) (*out_index)->host_only = true;
+    return st;
+}
+
+int lj_build_gapped_rmi_host_only(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves,
+                                  uint32_t slots_per_key, uint32_t flags,
+                                  lj_index** out_index) {
+    if (out_index) *out_index = nullptr;
+    if (slots_per_key < 1 || slots_per_key > kMaxSlotsPerKey) return LJ_ERR_ARG;
+    int st = build_common(r_keys_host, n, leaves, flags, slots_per_key, out_index);
     if (st == LJ_OK) (*out_index)->host_only = true;
     return st;
 }
 
 int lj_build_rmi(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves, uint32_t flags,
                  hipStream_t stream, lj_index** out_index) {
-    int st = build_common(r_keys_host, n, leaves, flags, out_index);
+    return build_device(r_keys_host, n, leaves, flags, 0, stream, out_index);
+}
+
+int lj_build_gapped_rmi(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves,
+                        uint32_t slots_per_key, uint32_t flags, hipStream_t stream,
+                        lj_index** out_index) {
+    if (out_index) *out_index = nullptr;
+    if (slots_per_key < 1 || slots_per_key > kMaxSlotsPerKey) return LJ_ERR_ARG;
+    return build_device(r_keys_host, n, leaves, flags, slots_per_key, stream, out_index);
+}
+
+}  // extern "C"
+
+namespace {
+
+int build_device(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves, uint32_t flags,
+                 uint32_t gap_factor, hipStream_t stream, lj_index** out_index) {
+    int st = build_common(r_keys_host, n, leaves, flags, gap_factor, out_index);
     if (st != LJ_OK) return st;
     lj_index* idx = *out_index;
     *out_index = nullptr;
@@ -105,15 +140,17 @@ int lj_build_rmi(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves, uint3
                                                                       : sizeof(lj::LeafF64));
     const uint64_t fbytes = idx->fences.size() * sizeof(uint64_t);
     const uint64_t bbytes = idx->bucket_lo.size() * sizeof(uint16_t);
+    const uint64_t sbytes = idx->slots.size() * sizeof(lj::GSlot);
     if (hipMalloc((void**)&idx->r_dev, rbytes) != hipSuccess ||
         hipMalloc(&idx->leaf_dev, lbytes) != hipSuccess ||
         (fbytes && hipMalloc((void**)&idx->fences_dev, fbytes) != hipSuccess) ||
-        (bbytes && hipMalloc((void**)&idx->bucket_lo_dev, bbytes) != hipSuccess)) {
+        (bbytes && hipMalloc((void**)&idx->bucket_lo_dev, bbytes) != hipSuccess) ||
+        (sbytes && hipMalloc((void**)&idx->slots_dev, sbytes) != hipSuccess)) {
         (void)hipGetLastError();
         lj_free_index(idx);
         return LJ_ERR_OOM;
     }
-    idx->device_bytes = rbytes + lbytes + fbytes + bbytes;
+    idx->device_bytes = rbytes + lbytes + fbytes + bbytes + sbytes;
     hipError_t e = hipSuccess;
     if (n) e = hipMemcpyAsync(idx->r_dev, r_keys_host, n * sizeof(uint64_t),
                               hipMemcpyHostToDevice, stream);
@@ -125,14 +162,22 @@ int lj_build_rmi(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves, uint3
     if (e == hipSuccess && bbytes)
         e = hipMemcpyAsync(idx->bucket_lo_dev, idx->bucket_lo.data(), bbytes,
                            hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && sbytes)
+        e = hipMemcpyAsync(idx->slots_dev, idx->slots.data(), sbytes, hipMemcpyHostToDevice,
+                           stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
         lj_free_index(idx);
         return LJ_ERR_DEVICE;
     }
+    std::vector<lj::GSlot>().swap(idx->slots);  // the device copy is the one probed
     *out_index = idx;
     return LJ_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 void lj_free_index(lj_index* idx) {
     if (!idx) return;
@@ -140,6 +185,7 @@ void lj_free_index(lj_index* idx) {
     if (idx->leaf_dev) (void)hipFree(idx->leaf_dev);
     if (idx->fences_dev) (void)hipFree(idx->fences_dev);
     if (idx->bucket_lo_dev) (void)hipFree(idx->bucket_lo_dev);
+    if (idx->slots_dev) (void)hipFree(idx->slots_dev);
     delete idx;
 }
 
@@ -241,15 +287,31 @@ int lj_index_get_stats(const lj_index* idx, lj_index_stats* o) {
     o->root_a0 = idx->root.a0;
     o->root_b0 = idx->root.b0;
     o->root_kmin = idx->root.kmin;
+    o->slots_per_key = idx->gap;
+    o->pad = 0;
+    o->nslots = idx->nslots;
     return LJ_OK;
+}
+
+int lj_gapped_slots_host(const lj_index* idx, uint64_t* keys, uint32_t* ridx, uint64_t cap,
+                         uint64_t* nslots_out) {
+    if (!idx || !idx->gap || idx->slots.size() != idx->nslots || !nslots_out) return LJ_ERR_ARG;
+    if (cap && (!keys || !ridx)) return LJ_ERR_ARG;
+    *nslots_out = idx->nslots;
+    const uint64_t k = std::min<uint64_t>(cap, idx->nslots);
+    for (uint64_t j = 0; j < k; ++j) {
+        keys[j] = idx->slots[j].key;
+        ridx[j] = idx->slots[j].ridx;
+    }
+    return cap >= idx->nslots ? LJ_OK : LJ_ERR_CAPACITY;
 }
 
 int lj_self_check(const lj_index* idx, uint64_t* viol_host, hipStream_t stream) {
     if (!idx || idx->host_only || !viol_host) return LJ_ERR_ARG;
     int st = check_device(idx);
     if (st != LJ_OK) return st;
-    uint64_t* d = nullptr;
-    if (hipMalloc((void**)&d, sizeof(uint64_t)) != hipSuccess) return LJ_ERR_OOM;
+    uint64_t* d = nullptr;  // violations, and a gapped index's key-slot count
+    if (hipMalloc((void**)&d, 2 * sizeof(uint64_t)) != hipSuccess) return LJ_ERR_OOM;
     hipError_t e = lj::launch_self_check(idx, d, stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(viol_host, d, sizeof(uint64_t), hipMemcpyDeviceToHost, stream);
@@ -292,7 +354,13 @@ int lj_predict_windows_host(const lj_index* idx, const uint64_t* keys, uint64_t 
             elo = lf.lo;
             ehi = lf.hi;
         }
-        if (cnt) {
+        if (cnt && idx->gap) {
+            // Gapped index: slot window [s, s + hi] of the predicted slot s.
+            int64_t rc = rel < 0 ? 0 : (rel > (int64_t)cnt - 1 ? (int64_t)cnt - 1 : rel);
+            pr = ((int64_t)pos0 + rc) * (int64_t)idx->gap;
+            lo = pr;
+            hi = std::min<int64_t>(pr + ehi, (int64_t)idx->nslots - 1);
+        } else if (cnt) {
             pr = (int64_t)pos0 + rel;
             int64_t a = (int64_t)rel + elo, b = (int64_t)rel + ehi;
             if (a < 0) a = 0;

@@ -112,8 +112,10 @@ void fit_leaves(const uint64_t* r, const std::vector<uint64_t>& pos0,
     });
 }
 
+// Search-window statistics over the keys of R (an RMI's windows are clipped
+// to the leaf's run; a gapped index's slot windows are not).
 template <class Leaf>
-void leaf_stats(const std::vector<Leaf>& lv, lj_index* idx) {
+void leaf_stats(const std::vector<Leaf>& lv, lj_index* idx, bool clip_to_run = true) {
     double wsum = 0;
     uint64_t wmax = 0;
     uint32_t ne = 0, mk = 0;
@@ -122,7 +124,7 @@ void leaf_stats(const std::vector<Leaf>& lv, lj_index* idx) {
         ++ne;
         mk = std::max(mk, lf.cnt);
         uint64_t w = (uint64_t)((int64_t)lf.hi - (int64_t)lf.lo + 1);
-        w = std::min<uint64_t>(w, lf.cnt);
+        if (clip_to_run) w = std::min<uint64_t>(w, lf.cnt);
         wsum += (double)w * lf.cnt;
         wmax = std::max(wmax, w);
     }
@@ -198,6 +200,62 @@ int fit_rmi(const uint64_t* r, uint64_t n, uint32_t L, uint32_t flags, lj_index*
         leaf_stats(idx->leaf64, idx);
     }
     return LJ_OK;
+}
+
+namespace {
+
+// Model-based insertion for one leaf arithmetic (Section III-A, "GRMI
+// Building": the RMI built over R places every key in the gapped array).
+template <class Leaf>
+int fit_gapped_leaves(const uint64_t* r, uint32_t G, std::vector<Leaf>& lv, lj_index* idx) {
+    const uint64_t n = idx->n;
+    // Predicted slot of every key; keys go in order, each to its predicted
+    // slot or, when taken, to the slot after the previous key, so the array
+    // stays sorted and equal keys stay adjacent.
+    std::vector<uint64_t> slot(n);
+    parallel_items(lv.size(), [&](uint64_t l) {
+        const Leaf& lf = lv[l];
+        for (uint64_t i = lf.pos0; i < (uint64_t)lf.pos0 + lf.cnt; ++i)
+            slot[i] = gapped_pred(lf, r[i], G);
+    });
+    uint64_t prev = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t pred = slot[i];
+        slot[i] = (i == 0 || pred > prev) ? pred : prev + 1;
+        prev = slot[i];
+    }
+    const uint64_t nslots = n ? std::max<uint64_t>(n * G, slot[n - 1] + 1) : 1;
+    if (nslots >= (1ull << 32)) return LJ_ERR_TOO_LARGE;
+    // Per leaf: the largest distance from a key's predicted slot to its slot.
+    parallel_items(lv.size(), [&](uint64_t l) {
+        Leaf& lf = lv[l];
+        if (lf.cnt == 0) return;  // keeps lo > hi: empty
+        uint64_t drift = 0;
+        for (uint64_t i = lf.pos0; i < (uint64_t)lf.pos0 + lf.cnt; ++i)
+            drift = std::max(drift, slot[i] - gapped_pred(lf, r[i], G));
+        lf.lo = 0;
+        lf.hi = (int32_t)std::min<uint64_t>(drift, 0x7FFFFFFF);
+    });
+    // Fill: keys with their positions; gaps with the next key of R.
+    idx->slots.assign(nslots, GSlot{~0ull, kGap, 0u});
+    for (uint64_t i = 0; i < n; ++i) idx->slots[slot[i]] = GSlot{r[i], (uint32_t)i, 0u};
+    uint64_t next = ~0ull;
+    for (uint64_t j = nslots; j-- > 0;) {
+        if (idx->slots[j].ridx != kGap) next = idx->slots[j].key;
+        else idx->slots[j].key = next;
+    }
+    idx->nslots = nslots;
+    idx->gap = G;
+    leaf_stats(lv, idx, false);
+    return LJ_OK;
+}
+
+}  // namespace
+
+int fit_gapped(const uint64_t* r, uint32_t G, lj_index* idx) {
+    if (G < 1) return LJ_ERR_ARG;
+    return leaf_fp32(idx->flags) ? fit_gapped_leaves(r, G, idx->leaf32, idx)
+                                 : fit_gapped_leaves(r, G, idx->leaf64, idx);
 }
 
 }  // namespace lj

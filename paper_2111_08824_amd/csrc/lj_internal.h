@@ -8,6 +8,22 @@
 #include "lj.h"
 #include "rmi_eval.h"
 
+namespace lj {
+
+// Slot of the gapped arrays of a gapped RMI (Section III-A, "GRMI
+// Structure"): the key and its payload (the key's position in R) side by
+// side, the gap bitmap folded into the payload, so that one 16-byte load
+// reads all three.  A gap holds the next key of R (UINT64_MAX after the
+// last one), which keeps the key array non-decreasing for the search.
+struct alignas(16) GSlot {
+    uint64_t key;
+    uint32_t ridx;  // position in R, or kGap
+    uint32_t pad;
+};
+constexpr uint32_t kGap = 0xFFFFFFFFu;
+
+}  // namespace lj
+
 struct lj_index {
     uint64_t n = 0;
     uint32_t leaves = 0;
@@ -32,6 +48,15 @@ struct lj_index {
     std::vector<uint64_t> fences;
     std::vector<uint16_t> bucket_lo;
 
+    // Gapped RMI: gap factor G (slots per key of R; 0 for a plain RMI), the
+    // number of slots and the slot array (host copy kept for host-only
+    // indexes).  A leaf's lo/hi then bound the slot of every key routed to it
+    // relative to its predicted slot: 0 <= slot - predicted <= hi.
+    uint32_t gap = 0;
+    uint64_t nslots = 0;
+    std::vector<lj::GSlot> slots;
+    lj::GSlot* slots_dev = nullptr;
+
     // device copies
     uint64_t* r_dev = nullptr;
     void* leaf_dev = nullptr;
@@ -49,12 +74,29 @@ inline bool leaf_fp32(uint32_t flags) { return (flags & 3u) == LJ_LEAF_FP32; }
 int fit_rmi(const uint64_t* r, uint64_t n, uint32_t leaves, uint32_t flags,
             lj_index* idx);
 
+// Turn a fitted RMI into a gapped RMI with G slots per key of R: model-based
+// insertion of R into the slot array and per-leaf slot bounds (host only).
+int fit_gapped(const uint64_t* r, uint32_t G, lj_index* idx);
+
+// Predicted slot of key x in a gapped index: the leaf's predicted position,
+// clamped into the leaf's run, times G.  The leaf must not be empty.
+template <class Leaf>
+__host__ __device__ inline uint64_t gapped_pred(const Leaf& lf, uint64_t x, uint32_t G) {
+    int64_t rel = predict_rel(lf, x);
+    if (rel < 0) rel = 0;
+    if (rel > (int64_t)lf.cnt - 1) rel = (int64_t)lf.cnt - 1;
+    return ((uint64_t)lf.pos0 + (uint64_t)rel) * G;
+}
+
 // Tile geometry of the fused probe kernel: kBlock threads, each holding
 // kItems outer keys (kItemsUnique when R has no duplicate keys, kItemsDup
-// otherwise, where the run scan and the LDS offsets need more room).
+// otherwise, where the run scan and the LDS offsets need more room;
+// kItemsGapped on a gapped index without duplicates, whose search state
+// needs more registers).
 constexpr int kBlock = 256;
 constexpr int kItemsUnique = 24;
 constexpr int kItemsDup = 16;
+constexpr int kItemsGapped = 8;
 constexpr int kItemsBinned = 16;  // search kernel of the binned probe (measured best)
 constexpr int kSetupChunk = 4;
 constexpr int kMinTile = kBlock * 4;  // smallest tile any launch uses
@@ -65,7 +107,7 @@ struct WsHeader {
     uint32_t tile_counter;  // dynamic tile ids
     uint32_t done_counter;  // tiles finished
     uint32_t err;           // non-zero: a wait bound was hit
-    uint32_t pad0;
+    uint32_t queue_count;   // binned probe of a gapped index: keys queued for the second pass
     uint64_t count;         // total pairs (internal count slot)
 };
 constexpr uint64_t kWsHeaderBytes = 256;
@@ -176,16 +218,21 @@ struct TileJob {
     uint32_t* done;        // tiles of this batch finished
     uint32_t* err;         // error flag shared by the launch
     uint32_t ntiles;
-    uint32_t kind;         // kJobFp64 | kJobDup
+    uint32_t kind;         // kJobFp64 | kJobDup | kJobExp | kJobGapped
     uint32_t kpl;          // keys per lane in this batch's tiles
+    const GSlot* slots;    // gapped index: slot array, its size and gap factor
+    uint32_t nslots;
+    uint32_t gap;
 };
 constexpr uint32_t kJobFp64 = 1u;
 constexpr uint32_t kJobDup = 2u;
 constexpr uint32_t kJobExp = 4u;
+constexpr uint32_t kJobGapped = 8u;
 
 inline uint32_t job_kind(const lj_index* idx) {
     return ((idx->flags & LJ_LEAF_FP64) ? kJobFp64 : 0u) | (idx->max_mult > 1 ? kJobDup : 0u) |
-           ((idx->flags & LJ_SEARCH_EXPONENTIAL) ? kJobExp : 0u);
+           ((idx->flags & LJ_SEARCH_EXPONENTIAL) ? kJobExp : 0u) |
+           (idx->gap ? kJobGapped : 0u);
 }
 
 // Kernel launchers (lj_kernels.hip).  Return hipSuccess or the launch error.
@@ -212,6 +259,7 @@ hipError_t launch_unpermute_count(const uint32_t* dest, const void* in, void* ou
                                   hipStream_t stream);
 hipError_t launch_set_u64(uint64_t* p, uint64_t v, hipStream_t stream);
 hipError_t launch_zero_words(uint64_t* p, uint64_t nwords, hipStream_t stream);
+// violations_dev: two words (the count, then scratch for a gapped index).
 hipError_t launch_self_check(const lj_index* idx, uint64_t* violations_dev,
                              hipStream_t stream);
 hipError_t launch_predict_windows(const lj_index* idx, const uint64_t* keys,

@@ -38,9 +38,7 @@ namespace lj {
 namespace {
 
 // Leaf records are read as whole 16-byte vectors.
-__device__ inline LeafF32 load_leaf(const LeafF32* p) {
-    const uint4* q = (const uint4*)p;
-    uint4 a = q[0], b = q[1];
+__device__ inline LeafF32 leaf_from(const uint4& a, const uint4& b) {
     LeafF32 l;
     l.base = (uint64_t)a.x | ((uint64_t)a.y << 32);
     l.slope = __uint_as_float(a.z);
@@ -52,9 +50,12 @@ __device__ inline LeafF32 load_leaf(const LeafF32* p) {
     return l;
 }
 
-__device__ inline LeafF64 load_leaf(const LeafF64* p) {
+__device__ inline LeafF32 load_leaf(const LeafF32* p) {
     const uint4* q = (const uint4*)p;
-    uint4 a = q[0], b = q[1], c = q[2];
+    return leaf_from(q[0], q[1]);
+}
+
+__device__ inline LeafF64 leaf_from(const uint4& a, const uint4& b, const uint4& c) {
     LeafF64 l;
     l.base = (uint64_t)a.x | ((uint64_t)a.y << 32);
     l.slope = __hiloint2double((int)a.w, (int)a.z);
@@ -65,6 +66,11 @@ __device__ inline LeafF64 load_leaf(const LeafF64* p) {
     l.hi = (int32_t)c.y;
     l.pad = 0;
     return l;
+}
+
+__device__ inline LeafF64 load_leaf(const LeafF64* p) {
+    const uint4* q = (const uint4*)p;
+    return leaf_from(q[0], q[1], q[2]);
 }
 
 // Shared memory of one tile; the duplicate path needs the per-key offsets
@@ -280,6 +286,162 @@ __device__ __forceinline__ void search_keys(const uint64_t* __restrict__ R, cons
     }
 }
 
+// Slots are read as whole 16-byte vectors: key, payload and gap flag.
+__device__ inline uint4 load_slot(const GSlot* p) { return *(const uint4*)p; }
+__device__ inline uint64_t slot_key(const uint4& v) {
+    return (uint64_t)v.x | ((uint64_t)v.y << 32);
+}
+
+// Steps 1-3 on a gapped index (Section III-A, "GRMI Lookup") for the keys
+// of one tile (layout as in search_keys): root model, leaf model, predicted
+// slot sp, and the search state of each key: the slots [a, b) not yet known
+// to hold a smaller key, starting as [sp, sp + the leaf's largest insertion
+// drift] (empty for an empty leaf or a key past the end of s), and the
+// gallop step.
+template <class Leaf, int kItems>
+__device__ __forceinline__ void gapped_setup(const uint32_t nslots, const uint32_t G,
+                                             const Leaf* leaves, const RootModel& root,
+                                             const uint64_t* s, const uint64_t m,
+                                             const uint64_t tbase, const uint32_t kpl,
+                                             uint64_t (&x)[kItems], uint32_t (&a)[kItems],
+                                             uint32_t (&b)[kItems], uint32_t (&step)[kItems]) {
+    const int tid = threadIdx.x;
+    uint32_t validmask = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const uint64_t q = tbase + (uint64_t)k * kBlock + tid;
+        const bool ok = (uint32_t)k < kpl && q < m;
+        validmask |= (ok ? 1u : 0u) << k;
+        x[k] = s[ok ? q : m - 1];
+    }
+#pragma unroll
+    for (int k0 = 0; k0 < kItems; k0 += kSetupChunk) {
+        Leaf lf[kSetupChunk];
+#pragma unroll
+        for (int u = 0; u < kSetupChunk; ++u) lf[u] = load_leaf(leaves + route(root, x[k0 + u]));
+#pragma unroll
+        for (int u = 0; u < kSetupChunk; ++u) {
+            const int k = k0 + u;
+            const bool live = ((validmask >> k) & 1u) && lf[u].cnt != 0;
+            const uint64_t sp = live ? gapped_pred(lf[u], x[k], G) : 0;
+            uint64_t e = sp + (uint64_t)(lf[u].hi < 0 ? 0 : lf[u].hi);
+            if (e > (uint64_t)nslots - 1) e = (uint64_t)nslots - 1;
+            a[k] = live ? (uint32_t)sp : 0;
+            b[k] = live ? (uint32_t)e + 1 : 0;
+            step[k] = 1;
+        }
+    }
+}
+
+// Up to kMaxSteps lockstep search steps of the gapped lookup for the keys of
+// a lane: each step probes one slot per unfinished key, galloping (slots
+// a, a + 1, a + 3, a + 7, ... relative to the last slot known to hold a
+// smaller key) until a slot holds a key >= x, then bisecting that bracket.
+// A key is done when a == b; b is then its lower bound in the slots from
+// sp on, bit k of eqmask says whether that slot is a key slot holding x,
+// and first[k] is its payload.
+template <int kItems, uint32_t kMaxSteps = 0>  // 0: until every key is done
+__device__ __forceinline__ void gapped_steps(const GSlot* __restrict__ slots,
+                                             const uint64_t (&x)[kItems],
+                                             uint32_t (&a)[kItems], uint32_t (&b)[kItems],
+                                             uint32_t (&step)[kItems], uint32_t& eqmask,
+                                             uint32_t (&first)[kItems]) {
+    static_assert(kItems <= 32, "eqmask holds one bit per key");
+    for (uint32_t it = 0; kMaxSteps == 0 || it < kMaxSteps; ++it) {
+        uint32_t any = 0;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) any |= a[k] < b[k] ? 1u : 0u;
+        if (!any) break;
+        uint4 v[kItems];
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const uint32_t g = a[k] - 1 + step[k];
+            const uint32_t p = step[k] ? (g < b[k] - 1 ? g : b[k] - 1) : a[k] + ((b[k] - a[k]) >> 1);
+            v[k] = load_slot(slots + (a[k] < b[k] ? p : 0u));
+        }
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const uint32_t g = a[k] - 1 + step[k];
+            const uint32_t p = step[k] ? (g < b[k] - 1 ? g : b[k] - 1) : a[k] + ((b[k] - a[k]) >> 1);
+            const uint32_t act = a[k] < b[k] ? 1u : 0u;
+            const uint64_t key = slot_key(v[k]);
+            const uint32_t lt = key < x[k] ? act : 0u;
+            const uint32_t ge = act ^ lt;
+            // A trailing gap holds UINT64_MAX: only a key slot is a match.
+            const uint32_t eq = key == x[k] && v[k].z != kGap ? 1u : 0u;
+            a[k] = lt ? p + 1 : a[k];
+            b[k] = ge ? p : b[k];
+            step[k] = lt ? step[k] * 2 : (ge ? 0u : step[k]);
+            eqmask = (eqmask & ~(ge << k)) | ((eq & ge) << k);
+            first[k] = ge ? v[k].z : first[k];
+        }
+    }
+}
+
+// Steps 1-4 on a gapped index for the keys of one tile: setup, the search
+// to the end, and (duplicates) the length of the match run.  The lower
+// bound found is the slot of the first copy of x when x is in R (every slot
+// between sp and it holds a smaller key), so its payload is the position of
+// that copy; copies fill the next slots.  On return first[k] is that
+// position and c[k] the number of copies (0 for a miss).
+template <class Leaf, bool kUnique, int kItems>
+__device__ __forceinline__ void search_keys_gapped(const GSlot* __restrict__ slots,
+                                                   const uint32_t nslots, const uint32_t G,
+                                                   const Leaf* leaves, const RootModel& root,
+                                                   const uint64_t* s, const uint64_t m,
+                                                   const uint64_t tbase, const uint32_t kpl,
+                                                   uint32_t (&first)[kItems],
+                                                   uint32_t (&c)[kItems]) {
+    uint64_t x[kItems];
+    uint32_t a[kItems], b[kItems], step[kItems];
+    uint32_t eqmask = 0;
+    gapped_setup<Leaf, kItems>(nslots, G, leaves, root, s, m, tbase, kpl, x, a, b, step);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) first[k] = 0;
+    gapped_steps<kItems>(slots, x, a, b, step, eqmask, first);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) c[k] = (eqmask >> k) & 1u;
+    if constexpr (!kUnique) {
+        // Copies of x sit in the slots after b: count them, four at a time.
+        uint32_t cur[kItems];
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) cur[k] = b[k] + 1;
+#pragma unroll
+        for (int k0 = 0; k0 < kItems; k0 += kSetupChunk) {
+            bool act[kSetupChunk];
+#pragma unroll
+            for (int u = 0; u < kSetupChunk; ++u)
+                act[u] = c[k0 + u] && cur[k0 + u] < nslots;
+            for (;;) {
+                bool anyact = false;
+#pragma unroll
+                for (int u = 0; u < kSetupChunk; ++u) anyact |= act[u];
+                if (!anyact) break;
+                uint4 v[kSetupChunk][4];
+#pragma unroll
+                for (int u = 0; u < kSetupChunk; ++u)
+#pragma unroll
+                    for (int w4 = 0; w4 < 4; ++w4) {
+                        const bool in = act[u] && cur[k0 + u] + w4 < nslots;
+                        v[u][w4] = load_slot(slots + (in ? cur[k0 + u] + w4 : 0u));
+                        if (!in) v[u][w4].x = ~(uint32_t)x[k0 + u];  // not equal to x
+                    }
+#pragma unroll
+                for (int u = 0; u < kSetupChunk; ++u) {
+                    bool run = act[u];
+#pragma unroll
+                    for (int w4 = 0; w4 < 4; ++w4) {
+                        run = run && slot_key(v[u][w4]) == x[k0 + u] && v[u][w4].z != kGap;
+                        c[k0 + u] += run ? 1u : 0u;
+                    }
+                    cur[k0 + u] += 4;
+                    act[u] = run && cur[k0 + u] < nslots;
+                }
+            }
+        }
+    }
+}
+
 // Steps 5-7 for one tile whose lower bounds and run lengths are known:
 // offsets, look-back, pair emission; then the tile is counted as done.
 // Without kLookBack the tile's output offset is given (excl_given) and the
@@ -401,24 +563,36 @@ __device__ __forceinline__ void emit_tile(const TileJob& j, const uint32_t tile,
     if constexpr (kLookBack) finish_tile(j);
 }
 
+// Last-mile search of a launch: binary or exponential search of R within
+// the RMI window, or the gapped index's search.
+constexpr int kSearchBinary = 0;
+constexpr int kSearchExp = 1;
+constexpr int kSearchGapped = 2;
+
 // Probe one tile of a batch (steps 1-7).
-template <class Leaf, bool kUnique, int kItems, bool kWithOffsets, bool kExp>
+template <class Leaf, bool kUnique, int kItems, bool kWithOffsets, int kSearch>
 __device__ __forceinline__ void probe_tile(const TileJob& j, const uint32_t tile,
                                            const uint32_t kpl,
                                            TileShared<kItems, kWithOffsets>& sh) {
     uint32_t first[kItems], c[kItems];
-    search_keys<Leaf, kUnique, kItems, kExp>(j.r, (const Leaf*)j.leaves, j.root, j.s, j.m,
-                                             (uint64_t)tile * kBlock * kpl, kpl, first, c);
+    if constexpr (kSearch == kSearchGapped)
+        search_keys_gapped<Leaf, kUnique, kItems>(j.slots, j.nslots, j.gap,
+                                                  (const Leaf*)j.leaves, j.root, j.s, j.m,
+                                                  (uint64_t)tile * kBlock * kpl, kpl, first, c);
+    else
+        search_keys<Leaf, kUnique, kItems, kSearch == kSearchExp>(
+            j.r, (const Leaf*)j.leaves, j.root, j.s, j.m, (uint64_t)tile * kBlock * kpl, kpl,
+            first, c);
     emit_tile<kUnique, kItems, kWithOffsets>(j, tile, kpl, sh, first, c);
 }
 
-template <class Leaf, bool kUnique, int kItems, bool kExp>
+template <class Leaf, bool kUnique, int kItems, int kSearch>
 __global__ __launch_bounds__(kBlock) void probe_join_kernel(TileJob j, uint32_t* tile_counter) {
     __shared__ uint32_t s_tile;
     __shared__ TileShared<kItems, !kUnique> sh;
     if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
     __syncthreads();
-    probe_tile<Leaf, kUnique, kItems, !kUnique, kExp>(j, s_tile, kItems, sh);
+    probe_tile<Leaf, kUnique, kItems, !kUnique, kSearch>(j, s_tile, kItems, sh);
 }
 
 // Search kernel of the binned probe: keys in bin order, tiles of kBlock *
@@ -426,27 +600,154 @@ __global__ __launch_bounds__(kBlock) void probe_join_kernel(TileJob j, uint32_t*
 // workgroup g works on range g % kXcds, so that each XCD's L2 holds the R
 // lines of its own few key ranges.  res[q] = lower bound of keys[q] when
 // found, else ~0u (unique R); res[q] = lower bound | count << 32, or 0
-// (duplicates).
-template <class Leaf, bool kUnique, int kItems, bool kExp>
-__global__ __launch_bounds__(kBlock) void probe_binned_kernel(const uint64_t* __restrict__ R,
-                                                              const Leaf* leaves,
-                                                              RootModel root,
-                                                              const uint64_t* keys, uint64_t m,
-                                                              uint32_t ntiles,
-                                                              uint32_t tiles_per_xcd,
-                                                              void* res) {
+// (duplicates).  A gapped index passes its slots, slot count and slots per
+// key as well.
+template <class Leaf, bool kUnique, int kItems, int kSearch>
+__global__ __launch_bounds__(kBlock) void probe_binned_kernel(
+    const uint64_t* __restrict__ R, const Leaf* leaves, RootModel root,
+    const GSlot* __restrict__ slots, uint32_t nslots, uint32_t G, const uint64_t* keys,
+    uint64_t m, uint32_t ntiles, uint32_t tiles_per_xcd, void* res) {
     const uint32_t slot = blockIdx.x / kXcds;
     const uint32_t tile = (blockIdx.x % kXcds) * tiles_per_xcd + slot;
     if (slot >= tiles_per_xcd || tile >= ntiles) return;
     const uint64_t tbase = (uint64_t)tile * kBlock * kItems;
     uint32_t first[kItems], c[kItems];
-    search_keys<Leaf, kUnique, kItems, kExp>(R, leaves, root, keys, m, tbase, kItems, first, c);
+    if constexpr (kSearch == kSearchGapped)
+        search_keys_gapped<Leaf, kUnique, kItems>(slots, nslots, G, leaves, root, keys, m, tbase,
+                                                  kItems, first, c);
+    else
+        search_keys<Leaf, kUnique, kItems, kSearch == kSearchExp>(R, leaves, root, keys, m,
+                                                                  tbase, kItems, first, c);
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const uint64_t q = tbase + (uint64_t)k * kBlock + threadIdx.x;
         if (q >= m) continue;
         if constexpr (kUnique) ((uint32_t*)res)[q] = c[k] ? first[k] : ~0u;
         else ((uint64_t*)res)[q] = c[k] ? (uint64_t)first[k] | ((uint64_t)c[k] << 32) : 0ull;
+    }
+}
+
+// Search kernels of the binned probe on a gapped index without duplicate
+// keys.  Most keys sit at their predicted slot or a few slots after it, a
+// few far away; a lockstep search over a tile runs as long as its slowest
+// key, so the search is split.  First pass: every key gets kFirstSteps
+// lockstep steps; a key that is then done writes its result (layout of
+// probe_binned_kernel), the others go to a queue as (position in keys,
+// a, b).  Second pass (gapped_queue_kernel): the queued keys, now dense,
+// bisect their remaining slot range [a, b).  A wave whose keys do not fit
+// in the queue finishes them in the first pass and marks any queue entries
+// it took as void.
+template <class Leaf, int kItems, uint32_t kFirstSteps>
+__global__ __launch_bounds__(kBlock) void probe_binned_gapped_kernel(
+    const Leaf* leaves, RootModel root, const GSlot* __restrict__ slots, uint32_t nslots,
+    uint32_t G, const uint64_t* keys, uint64_t m, uint32_t ntiles, uint32_t tiles_per_xcd,
+    uint32_t* res, uint4* queue, uint32_t qcap, uint32_t* qcount) {
+    const uint32_t wslot = blockIdx.x / kXcds;
+    const uint32_t tile = (blockIdx.x % kXcds) * tiles_per_xcd + wslot;
+    if (wslot >= tiles_per_xcd || tile >= ntiles) return;
+    const int lane = threadIdx.x & 63;
+    const uint64_t tbase = (uint64_t)tile * kBlock * kItems;
+    uint64_t x[kItems];
+    uint32_t a[kItems], b[kItems], step[kItems], first[kItems];
+    uint32_t eqmask = 0;
+    gapped_setup<Leaf, kItems>(nslots, G, leaves, root, keys, m, tbase, kItems, x, a, b, step);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) first[k] = 0;
+    gapped_steps<kItems, kFirstSteps>(slots, x, a, b, step, eqmask, first);
+
+    // Reserve queue entries for the wave's unfinished keys.
+    uint32_t open = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const bool u = a[k] < b[k];
+        open |= (u ? 1u : 0u) << k;
+        total += (uint32_t)__popcll(__ballot(u));
+    }
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (total) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(qcount, total);
+        base = (uint32_t)__shfl((int)base, 0, 64);
+        const bool fits = (uint64_t)base + total <= qcap;
+        uint32_t off = base;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const bool u = (open >> k) & 1u;
+            const uint64_t mask = __ballot(u);
+            const uint32_t e = off + (uint32_t)__popcll(mask & lt);
+            if (u && e < qcap) {
+                const uint32_t q = (uint32_t)(tbase + (uint64_t)k * kBlock + threadIdx.x);
+                queue[e] = fits ? make_uint4(q, a[k], b[k], 0u) : make_uint4(~0u, 0u, 0u, 0u);
+            }
+            off += (uint32_t)__popcll(mask);
+        }
+        if (!fits) {  // the whole wave finishes here (a wave-uniform branch)
+            gapped_steps<kItems>(slots, x, a, b, step, eqmask, first);
+            open = 0;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const uint64_t q = tbase + (uint64_t)k * kBlock + threadIdx.x;
+        if (q < m && !((open >> k) & 1u)) res[q] = ((eqmask >> k) & 1u) ? first[k] : ~0u;
+    }
+}
+
+// Second pass of the gapped search: queued keys in tiles of kBlock * kItems
+// entries, dealt to the workgroups in turn.  Each key bisects [a, b); its
+// lower bound b is then a slot holding a key >= x, or the end of its slot
+// window, so the key slot of x is at b when x is in R (R has no duplicate
+// keys: x occupies one slot, inside the window).
+template <int kItems>
+__global__ __launch_bounds__(kBlock) void gapped_queue_kernel(const GSlot* __restrict__ slots,
+                                                              uint32_t nslots,
+                                                              const uint64_t* keys,
+                                                              const uint4* queue, uint32_t qcap,
+                                                              const uint32_t* qcount,
+                                                              uint32_t* res) {
+    const uint32_t n = *qcount < qcap ? *qcount : qcap;
+    const uint32_t per_tile = kBlock * kItems;
+    for (uint32_t t0 = blockIdx.x * per_tile; t0 < n; t0 += gridDim.x * per_tile) {
+        uint32_t q[kItems], a[kItems], b[kItems];
+        uint64_t x[kItems];
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const uint32_t e = t0 + (uint32_t)k * kBlock + threadIdx.x;
+            const uint4 v = e < n ? queue[e] : make_uint4(~0u, 0u, 0u, 0u);
+            q[k] = v.x;
+            a[k] = v.y;
+            b[k] = v.z;
+        }
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) x[k] = q[k] != ~0u ? keys[q[k]] : 0ull;
+        for (;;) {
+            uint32_t any = 0;
+#pragma unroll
+            for (int k = 0; k < kItems; ++k) any |= a[k] < b[k] ? 1u : 0u;
+            if (!any) break;
+            uint4 v[kItems];
+#pragma unroll
+            for (int k = 0; k < kItems; ++k)
+                v[k] = load_slot(slots + (a[k] < b[k] ? a[k] + ((b[k] - a[k]) >> 1) : 0u));
+#pragma unroll
+            for (int k = 0; k < kItems; ++k) {
+                const uint32_t p = a[k] + ((b[k] - a[k]) >> 1);
+                const bool act = a[k] < b[k];
+                const bool lt = slot_key(v[k]) < x[k];
+                a[k] = act && lt ? p + 1 : a[k];
+                b[k] = act && !lt ? p : b[k];
+            }
+        }
+        uint4 v[kItems];
+#pragma unroll
+        for (int k = 0; k < kItems; ++k)
+            v[k] = load_slot(slots + (q[k] != ~0u && b[k] < nslots ? b[k] : 0u));
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            if (q[k] == ~0u) continue;
+            const bool hit = b[k] < nslots && slot_key(v[k]) == x[k] && v[k].z != kGap;
+            res[q[k]] = hit ? v[k].z : ~0u;
+        }
     }
 }
 
@@ -510,17 +811,57 @@ __global__ void self_check_kernel(const uint64_t* R, uint64_t n, const Leaf* lea
     }
 }
 
+// Gapped index: every key slot must hold R at its payload position and sit
+// inside its slot window; key slots are counted into nkeys.
+template <class Leaf>
+__global__ void self_check_gapped_kernel(const uint64_t* R, uint64_t n, const GSlot* slots,
+                                         uint64_t nslots, uint32_t G, const Leaf* leaves,
+                                         RootModel root, unsigned long long* viol,
+                                         unsigned long long* nkeys) {
+    uint32_t bad = 0, keys = 0;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nslots;
+         j += (uint64_t)gridDim.x * blockDim.x) {
+        const uint4 v = load_slot(slots + j);
+        if (v.z == kGap) continue;
+        ++keys;
+        const uint64_t x = slot_key(v);
+        const Leaf lf = leaves[route(root, x)];
+        bool ok = v.z < n && R[v.z] == x && lf.cnt != 0 && v.z >= lf.pos0 &&
+                  v.z < (uint64_t)lf.pos0 + lf.cnt;
+        if (ok) {
+            const uint64_t sp = gapped_pred(lf, x, G);
+            ok = j >= sp && j - sp <= (uint64_t)(lf.hi < 0 ? 0 : lf.hi);
+        }
+        bad += ok ? 0u : 1u;
+    }
+    if (bad) atomicAdd(viol, (unsigned long long)bad);
+    if (keys) atomicAdd(nkeys, (unsigned long long)keys);
+}
+
+// viol[0] += |nkeys - n|.
+__global__ void finish_gapped_check_kernel(unsigned long long* viol, const unsigned long long* nkeys,
+                                           uint64_t n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        viol[0] += *nkeys > n ? *nkeys - n : n - *nkeys;
+}
+
 template <class Leaf>
 __global__ void predict_windows_kernel(const uint64_t* keys, uint64_t m, const Leaf* leaves,
-                                       RootModel root, uint32_t* leaf_out, int64_t* pred,
-                                       int64_t* wlo, int64_t* whi) {
+                                       RootModel root, uint32_t G, uint64_t nslots,
+                                       uint32_t* leaf_out, int64_t* pred, int64_t* wlo,
+                                       int64_t* whi) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
          i += (uint64_t)gridDim.x * blockDim.x) {
         uint64_t x = keys[i];
         uint32_t l = route(root, x);
         const Leaf lf = leaves[l];
         int64_t lo = 1, hi = 0, pr = -1;
-        if (lf.cnt != 0) {
+        if (lf.cnt != 0 && G) {
+            pr = (int64_t)gapped_pred(lf, x, G);
+            lo = pr;
+            hi = pr + (lf.hi < 0 ? 0 : lf.hi);
+            if (hi > (int64_t)nslots - 1) hi = (int64_t)nslots - 1;
+        } else if (lf.cnt != 0) {
             int64_t rel = predict_rel(lf, x);
             pr = (int64_t)lf.pos0 + rel;
             int64_t a = rel + lf.lo, b = rel + lf.hi;
@@ -558,26 +899,26 @@ hipError_t launch_zero_words(uint64_t* p, uint64_t nwords, hipStream_t stream) {
 
 namespace {
 
-template <int kItems, bool kExp>
+template <int kItems, int kSearch>
 hipError_t launch_probe_items(const TileJob& j, uint32_t* ctr, hipStream_t stream) {
     dim3 grid(j.ntiles), block(kBlock);
     switch (j.kind & (kJobFp64 | kJobDup)) {
         case 0:
-            hipLaunchKernelGGL((probe_join_kernel<LeafF32, true, kItems, kExp>), grid, block, 0,
+            hipLaunchKernelGGL((probe_join_kernel<LeafF32, true, kItems, kSearch>), grid, block, 0,
                                stream, j, ctr);
             break;
         case kJobDup:
             if constexpr (kItems <= kItemsDup)
-                hipLaunchKernelGGL((probe_join_kernel<LeafF32, false, kItems, kExp>), grid, block,
+                hipLaunchKernelGGL((probe_join_kernel<LeafF32, false, kItems, kSearch>), grid, block,
                                    0, stream, j, ctr);
             break;
         case kJobFp64:
-            hipLaunchKernelGGL((probe_join_kernel<LeafF64, true, kItems, kExp>), grid, block, 0,
+            hipLaunchKernelGGL((probe_join_kernel<LeafF64, true, kItems, kSearch>), grid, block, 0,
                                stream, j, ctr);
             break;
         default:
             if constexpr (kItems <= kItemsDup)
-                hipLaunchKernelGGL((probe_join_kernel<LeafF64, false, kItems, kExp>), grid, block,
+                hipLaunchKernelGGL((probe_join_kernel<LeafF64, false, kItems, kSearch>), grid, block,
                                    0, stream, j, ctr);
             break;
     }
@@ -592,15 +933,75 @@ bool probe_kpl_supported(uint32_t kpl, bool dup) {
 
 namespace {
 
-template <class Leaf, bool kUnique, bool kExp>
+// The index's fields of a TileJob.
+TileJob index_job(const lj_index* idx) {
+    TileJob j{};
+    j.r = idx->r_dev;
+    j.leaves = idx->leaf_dev;
+    j.root = idx->root;
+    j.kind = job_kind(idx);
+    j.slots = idx->slots_dev;
+    j.nslots = (uint32_t)idx->nslots;
+    j.gap = idx->gap;
+    return j;
+}
+
+int search_mode(uint32_t kind) {
+    return (kind & kJobGapped) ? kSearchGapped : (kind & kJobExp) ? kSearchExp : kSearchBinary;
+}
+
+template <class Leaf, bool kUnique, int kSearch>
 void launch_binned_search(const lj_index* idx, const uint64_t* keys, uint64_t m, void* res,
                           hipStream_t stream) {
     constexpr int kItems = kItemsBinned;
     const uint32_t nt = (uint32_t)num_tiles(m, (uint64_t)kBlock * kItems);
     const uint32_t per = (nt + kXcds - 1) / kXcds;
-    hipLaunchKernelGGL((probe_binned_kernel<Leaf, kUnique, kItems, kExp>), dim3(per * kXcds),
+    hipLaunchKernelGGL((probe_binned_kernel<Leaf, kUnique, kItems, kSearch>), dim3(per * kXcds),
                        dim3(kBlock), 0, stream, idx->r_dev, (const Leaf*)idx->leaf_dev,
-                       idx->root, keys, m, nt, per, res);
+                       idx->root, idx->slots_dev, (uint32_t)idx->nslots, idx->gap, keys, m, nt,
+                       per, res);
+}
+
+// Steps of the first pass of the two-pass gapped search, and keys per lane
+// of its second pass.
+constexpr uint32_t kGappedFirstSteps = 3;
+constexpr int kGappedFirstItems = 16;
+constexpr int kGappedQueueItems = 8;
+
+// Two-pass search of a gapped index without duplicate keys; the queue lives
+// in the workspace's bin arrays, which the partition no longer needs.
+template <class Leaf>
+void launch_binned_gapped(const lj_index* idx, const uint64_t* keys, uint64_t m, void* res,
+                          void* ws, const BinnedWs& L, hipStream_t stream) {
+    constexpr int kItems = kGappedFirstItems;
+    const uint32_t nt = (uint32_t)num_tiles(m, (uint64_t)kBlock * kItems);
+    const uint32_t per = (nt + kXcds - 1) / kXcds;
+    uint4* queue = (uint4*)((char*)ws + L.bins_s);
+    const uint32_t qcap = (uint32_t)((L.p1 - L.bins_s) / sizeof(uint4));
+    uint32_t* qcount = &((WsHeader*)ws)->queue_count;
+    hipLaunchKernelGGL((probe_binned_gapped_kernel<Leaf, kItems, kGappedFirstSteps>),
+                       dim3(per * kXcds), dim3(kBlock), 0, stream, (const Leaf*)idx->leaf_dev,
+                       idx->root, idx->slots_dev, (uint32_t)idx->nslots, idx->gap, keys, m, nt,
+                       per, (uint32_t*)res, queue, qcap, qcount);
+    const uint32_t qt = (uint32_t)num_tiles(qcap, (uint64_t)kBlock * kGappedQueueItems);
+    const uint32_t grid = qt < 2048u ? (qt ? qt : 1u) : 2048u;
+    hipLaunchKernelGGL(gapped_queue_kernel<kGappedQueueItems>, dim3(grid), dim3(kBlock), 0,
+                       stream, idx->slots_dev, (uint32_t)idx->nslots, keys,
+                       (const uint4*)queue, qcap, (const uint32_t*)qcount, (uint32_t*)res);
+}
+
+template <class Leaf, bool kUnique>
+void launch_binned_search_any(int search, const lj_index* idx, const uint64_t* keys,
+                              uint64_t m, void* res, void* ws, const BinnedWs& L,
+                              hipStream_t stream) {
+    if (search == kSearchGapped && kUnique)
+        launch_binned_gapped<Leaf>(idx, keys, m, res, ws, L, stream);
+    else if (search == kSearchGapped)
+        launch_binned_search<Leaf, kUnique, kSearchGapped>(idx, keys, m, res, stream);
+    else if (search == kSearchExp)
+        launch_binned_search<Leaf, kUnique, kSearchExp>(idx, keys, m, res, stream);
+    else
+        launch_binned_search<Leaf, kUnique, kSearchBinary>(idx, keys, m, res, stream);
 }
 
 // Binned probe: partition S by key range, search in that order, put the
@@ -625,16 +1026,16 @@ hipError_t launch_probe_binned(const lj_index* idx, const uint64_t* s, uint64_t 
         e = hipEventRecord(ev0, stream);
         if (e != hipSuccess) return e;
     }
-    const bool ex = (kind & kJobExp) != 0;
+    const int search = search_mode(kind);
     const bool f64 = (kind & kJobFp64) != 0;
-    if (!f64 && !dup) ex ? launch_binned_search<LeafF32, true, true>(idx, keys, m, res2, stream)
-                         : launch_binned_search<LeafF32, true, false>(idx, keys, m, res2, stream);
-    else if (!f64) ex ? launch_binned_search<LeafF32, false, true>(idx, keys, m, res2, stream)
-                      : launch_binned_search<LeafF32, false, false>(idx, keys, m, res2, stream);
-    else if (!dup) ex ? launch_binned_search<LeafF64, true, true>(idx, keys, m, res2, stream)
-                      : launch_binned_search<LeafF64, true, false>(idx, keys, m, res2, stream);
-    else ex ? launch_binned_search<LeafF64, false, true>(idx, keys, m, res2, stream)
-            : launch_binned_search<LeafF64, false, false>(idx, keys, m, res2, stream);
+    if (!f64 && !dup)
+        launch_binned_search_any<LeafF32, true>(search, idx, keys, m, res2, ws, L, stream);
+    else if (!f64)
+        launch_binned_search_any<LeafF32, false>(search, idx, keys, m, res2, ws, L, stream);
+    else if (!dup)
+        launch_binned_search_any<LeafF64, true>(search, idx, keys, m, res2, ws, L, stream);
+    else
+        launch_binned_search_any<LeafF64, false>(search, idx, keys, m, res2, ws, L, stream);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev1) {
@@ -678,7 +1079,7 @@ hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m, lj_p
     if (uses_binned(idx, m, mode))
         return launch_probe_binned(idx, s, m, out, cap, count_dev, ws, stream, ev0, ev1);
     const uint32_t kind = job_kind(idx);
-    if (kpl == 0) kpl = (kind & kJobDup) ? kItemsDup : kItemsUnique;
+    if (kpl == 0) kpl = (kind & kJobDup) ? kItemsDup : (kind & kJobGapped) ? kItemsGapped : kItemsUnique;
     if (!probe_kpl_supported(kpl, (kind & kJobDup) != 0)) return hipErrorInvalidValue;
     const uint64_t nt = num_tiles(m, (uint64_t)kBlock * kpl);
     const uint64_t words = (kWsHeaderBytes + nt * 8) / 8;
@@ -686,10 +1087,7 @@ hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m, lj_p
     if (e != hipSuccess) return e;
 
     WsHeader* hdr = (WsHeader*)ws;
-    TileJob j;
-    j.r = idx->r_dev;
-    j.leaves = idx->leaf_dev;
-    j.root = idx->root;
+    TileJob j = index_job(idx);
     j.s = s;
     j.m = m;
     j.out = out;
@@ -707,24 +1105,40 @@ hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m, lj_p
         if (e != hipSuccess) return e;
     }
     uint32_t* ctr = &hdr->tile_counter;
-    const bool ex = (kind & kJobExp) != 0;
+    const int search = search_mode(kind);
+#define LJ_ITEMS(K)                                                          \
+    e = search == kSearchGapped ? launch_probe_items<K, kSearchGapped>(j, ctr, stream) \
+        : search == kSearchExp  ? launch_probe_items<K, kSearchExp>(j, ctr, stream)    \
+                                : launch_probe_items<K, kSearchBinary>(j, ctr, stream)
     switch (kpl) {
-        case 4: e = ex ? launch_probe_items<4, true>(j, ctr, stream)
-                       : launch_probe_items<4, false>(j, ctr, stream); break;
-        case 8: e = ex ? launch_probe_items<8, true>(j, ctr, stream)
-                       : launch_probe_items<8, false>(j, ctr, stream); break;
-        case 16: e = ex ? launch_probe_items<16, true>(j, ctr, stream)
-                        : launch_probe_items<16, false>(j, ctr, stream); break;
-        default: e = ex ? launch_probe_items<24, true>(j, ctr, stream)
-                        : launch_probe_items<24, false>(j, ctr, stream); break;
+        case 4: LJ_ITEMS(4); break;
+        case 8: LJ_ITEMS(8); break;
+        case 16: LJ_ITEMS(16); break;
+        default: LJ_ITEMS(24); break;
     }
+#undef LJ_ITEMS
     if (e != hipSuccess) return e;
     if (ev1) e = hipEventRecord(ev1, stream);
     return e;
 }
 
 hipError_t launch_self_check(const lj_index* idx, uint64_t* viol, hipStream_t stream) {
-    hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, stream, viol, (uint64_t)1);
+    hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, stream, viol, (uint64_t)2);
+    if (idx->gap) {
+        unsigned long long* v = (unsigned long long*)viol;
+        const unsigned gs = grid_for(idx->nslots, 256);
+        if (leaf_fp32(idx->flags))
+            hipLaunchKernelGGL(self_check_gapped_kernel<LeafF32>, dim3(gs), dim3(256), 0, stream,
+                               idx->r_dev, idx->n, idx->slots_dev, idx->nslots, idx->gap,
+                               (const LeafF32*)idx->leaf_dev, idx->root, v, v + 1);
+        else
+            hipLaunchKernelGGL(self_check_gapped_kernel<LeafF64>, dim3(gs), dim3(256), 0, stream,
+                               idx->r_dev, idx->n, idx->slots_dev, idx->nslots, idx->gap,
+                               (const LeafF64*)idx->leaf_dev, idx->root, v, v + 1);
+        hipLaunchKernelGGL(finish_gapped_check_kernel, dim3(1), dim3(64), 0, stream, v,
+                           (const unsigned long long*)(v + 1), idx->n);
+        return hipGetLastError();
+    }
     unsigned g = grid_for(idx->n, 256);
     if (idx->n == 0) return hipGetLastError();
     if (leaf_fp32(idx->flags))
@@ -745,12 +1159,12 @@ hipError_t launch_predict_windows(const lj_index* idx, const uint64_t* keys, uin
     unsigned g = grid_for(m, 256);
     if (leaf_fp32(idx->flags))
         hipLaunchKernelGGL(predict_windows_kernel<LeafF32>, dim3(g), dim3(256), 0, stream,
-                           keys, m, (const LeafF32*)idx->leaf_dev, idx->root, leaf, pred, wlo,
-                           whi);
+                           keys, m, (const LeafF32*)idx->leaf_dev, idx->root, idx->gap,
+                           idx->nslots, leaf, pred, wlo, whi);
     else
         hipLaunchKernelGGL(predict_windows_kernel<LeafF64>, dim3(g), dim3(256), 0, stream,
-                           keys, m, (const LeafF64*)idx->leaf_dev, idx->root, leaf, pred, wlo,
-                           whi);
+                           keys, m, (const LeafF64*)idx->leaf_dev, idx->root, idx->gap,
+                           idx->nslots, leaf, pred, wlo, whi);
     return hipGetLastError();
 }
 

@@ -40,7 +40,9 @@ EXPORTED = (
     "lj_batch_plan_create", "lj_batch_plan_run", "lj_batch_plan_destroy", "lj_batch_autotune",
     "lj_server_default_config", "lj_server_create", "lj_server_submit",
     "lj_server_submit_device", "lj_server_wait", "lj_server_get_stats", "lj_server_destroy",
+    "lj_build_gapped_rmi", "lj_build_gapped_rmi_host_only", "lj_gapped_slots_host",
 )
+GAP_SLOT = 0xFFFFFFFF  # payload of a gap slot in lj_gapped_slots_host
 
 
 class LJError(RuntimeError):
@@ -63,6 +65,9 @@ class lj_index_stats(ctypes.Structure):
         ("root_a0", ctypes.c_double),
         ("root_b0", ctypes.c_double),
         ("root_kmin", ctypes.c_uint64),
+        ("slots_per_key", ctypes.c_uint32),
+        ("pad", ctypes.c_uint32),
+        ("nslots", ctypes.c_uint64),
     ]
 
 
@@ -140,6 +145,9 @@ def lib() -> ctypes.CDLL:
         vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
         L.lj_build_rmi.argtypes = [vp, u64, u32, u32, vp, ctypes.POINTER(vp)]
         L.lj_build_rmi_host_only.argtypes = [vp, u64, u32, u32, ctypes.POINTER(vp)]
+        L.lj_build_gapped_rmi.argtypes = [vp, u64, u32, u32, u32, vp, ctypes.POINTER(vp)]
+        L.lj_build_gapped_rmi_host_only.argtypes = [vp, u64, u32, u32, u32, ctypes.POINTER(vp)]
+        L.lj_gapped_slots_host.argtypes = [vp, vp, vp, u64, ctypes.POINTER(u64)]
         L.lj_free_index.argtypes = [vp]
         L.lj_free_index.restype = None
         L.lj_probe_join.argtypes = [vp, vp, u64, vp, u64, ctypes.POINTER(u64), vp]
@@ -256,6 +264,41 @@ def lj_build_rmi_host_only(r_keys, leaves: int, flags: int = LJ_LEAF_FP32) -> In
     _check(lib().lj_build_rmi_host_only(R.ctypes.data if len(R) else None, len(R), leaves,
                                         flags, ctypes.byref(h)), "lj_build_rmi_host_only")
     return Index(h.value, True)
+
+
+def lj_build_gapped_rmi(r_keys, leaves: int, slots_per_key: int = 4, flags: int = LJ_LEAF_FP32,
+                        stream=None) -> Index:
+    """Build a gapped RMI over host array r_keys (sorted uint64)."""
+    R = _host_u64(r_keys)
+    h = ctypes.c_void_p()
+    _check(lib().lj_build_gapped_rmi(R.ctypes.data if len(R) else None, len(R), leaves,
+                                     slots_per_key, flags, _stream_ptr(stream), ctypes.byref(h)),
+           "lj_build_gapped_rmi")
+    return Index(h.value, False)
+
+
+def lj_build_gapped_rmi_host_only(r_keys, leaves: int, slots_per_key: int = 4,
+                                  flags: int = LJ_LEAF_FP32) -> Index:
+    R = _host_u64(r_keys)
+    h = ctypes.c_void_p()
+    _check(lib().lj_build_gapped_rmi_host_only(R.ctypes.data if len(R) else None, len(R),
+                                               leaves, slots_per_key, flags, ctypes.byref(h)),
+           "lj_build_gapped_rmi_host_only")
+    return Index(h.value, True)
+
+
+def lj_gapped_slots_host(index: Index):
+    """(keys uint64[nslots], ridx uint32[nslots]) of a host-only gapped index;
+    a gap has ridx == GAP_SLOT and holds the next key of R."""
+    n = ctypes.c_uint64()
+    st = lib().lj_gapped_slots_host(index.handle, None, None, 0, ctypes.byref(n))
+    if st not in (LJ_OK, LJ_ERR_CAPACITY):
+        _check(st, "lj_gapped_slots_host")
+    keys = np.empty(n.value, dtype=np.uint64)
+    ridx = np.empty(n.value, dtype=np.uint32)
+    _check(lib().lj_gapped_slots_host(index.handle, keys.ctypes.data, ridx.ctypes.data, n.value,
+                                      ctypes.byref(n)), "lj_gapped_slots_host")
+    return keys, ridx
 
 
 def lj_probe_join(index: Index, s_keys_dev, out_pairs_dev=None, stream=None):

@@ -1,6 +1,7 @@
 """Full-size parity on the lognormal / Zipf workload (2e8 x 2e8, 2^20 leaves),
 probed the way the benchmark probes it (FP32 leaves, synchronous probe, with
-and without the binned probe).
+and without the binned probe, on a plain RMI and on a gapped RMI with 4
+slots per key).
 
 The oracle's full sort-merge is too slow on the host at this size, so the
 output is checked by properties that pin it exactly:
@@ -20,7 +21,18 @@ import workloads
 from paper_2111_08824_amd import lj
 
 pytestmark = pytest.mark.gpu
-MODES = [lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP32 | lj.LJ_PROBE_BINNED]
+# (flags, slots per key of a gapped RMI; 0 = plain RMI)
+MODES = [(lj.LJ_LEAF_FP32, 0), (lj.LJ_LEAF_FP32 | lj.LJ_PROBE_BINNED, 0),
+         (lj.LJ_LEAF_FP32, 4), (lj.LJ_LEAF_FP32 | lj.LJ_PROBE_BINNED, 4)]
+
+
+def build(w, mode):
+    flags, spk = mode
+    print(f"[fullsize] building index (fp32 leaves, {w.leaves}, flags {flags}, "
+          f"slots/key {spk})", flush=True)
+    if spk:
+        return lj.lj_build_gapped_rmi(w.R, w.leaves, spk, flags)
+    return lj.lj_build_rmi(w.R, w.leaves, flags)
 
 
 @pytest.fixture(scope="module")
@@ -40,12 +52,11 @@ def c3():
     return w, want
 
 
-@pytest.mark.parametrize("flags", MODES)
-def test_lognormal_zipf_200m_full_size(c2, flags):
+@pytest.mark.parametrize("mode", MODES)
+def test_lognormal_zipf_200m_full_size(c2, mode):
     import torch
     w = c2
-    print(f"[fullsize] building index (fp32 leaves, 2^20, flags {flags})", flush=True)
-    ix = lj.lj_build_rmi(w.R, w.leaves, flags)
+    ix = build(w, mode)
     assert lj.lj_self_check(ix) == 0
     s = lj.to_device_keys(w.S)
     out = torch.empty((len(w.S), 2), dtype=torch.int32, device="cuda")
@@ -69,8 +80,8 @@ def test_lognormal_zipf_200m_full_size(c2, flags):
     assert np.array_equal(ri[pos_c][emitted], first[emitted].astype(np.int64))
 
 
-@pytest.mark.parametrize("flags", MODES)
-def test_dup_runs_100m_full_size(c3, flags):
+@pytest.mark.parametrize("mode", MODES)
+def test_dup_runs_100m_full_size(c3, mode):
     """1e8 rows of seq_h values repeated U{1..16} times, 1e8 outer keys with
     70% hits: about 6e8 pairs.  Exact by: every pair matches, pairs strictly
     increase in (s, r), and their number equals the count invariant
@@ -79,9 +90,8 @@ def test_dup_runs_100m_full_size(c3, flags):
     oracle's equal_range."""
     import torch
     w, want = c3
-    print(f"[fullsize] building index (fp32 leaves, {w.leaves}, flags {flags}); "
-          f"expecting {want} pairs", flush=True)
-    ix = lj.lj_build_rmi(w.R, w.leaves, flags)
+    print(f"[fullsize] expecting {want} pairs", flush=True)
+    ix = build(w, mode)
     assert lj.lj_self_check(ix) == 0
     s = lj.to_device_keys(w.S)
     out = torch.empty((want, 2), dtype=torch.int32, device="cuda")

@@ -1,0 +1,179 @@
+"""GPU parity of the gapped RMI (Section III-A, "Gapped RMI"): probes of a
+gapped index through the C ABI, in every probe form (fused direct probe,
+binned probe, batched plan, serving loop), compared element by element with
+the oracle's sort-merge join on the same seeded inputs.  The join output is
+integer index work, so the bar is exact equality in (s_idx, r_idx) order;
+the device self-check must also find every key slot of R intact and inside
+its slot window."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from paper_2111_08824_amd import lj
+
+pytestmark = pytest.mark.gpu
+
+U64MAX = 2**64 - 1
+BIN = lj.LJ_PROBE_BINNED
+FLAGS = [lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP64, lj.LJ_LEAF_FP32 | BIN, lj.LJ_LEAF_FP64 | BIN]
+
+
+def assert_gapped_parity(R, S, leaves, flags, spk=4, label=""):
+    print(f"[gapped] {label} n={len(R)} m={len(S)} leaves={leaves} flags={flags} "
+          f"slots/key={spk}", flush=True)
+    R = np.asarray(R, dtype=np.uint64)
+    S = np.asarray(S, dtype=np.uint64)
+    ix = lj.lj_build_gapped_rmi(R, leaves, spk, flags)
+    assert ix.stats.slots_per_key == spk
+    assert lj.lj_self_check(ix) == 0
+    got = lj.probe(ix, lj.to_device_keys(S)).cpu().numpy().view(np.uint32).reshape(-1, 2)
+    want = oracle.sort_merge_join(R, S)
+    assert got.shape == want.shape, (got.shape, want.shape)
+    assert np.array_equal(got, want)
+    return ix, got
+
+
+@pytest.mark.parametrize("flags", FLAGS)
+def test_workloads(flags):
+    w = workloads.c1_uniform(scale=0.5)
+    assert_gapped_parity(w.R, w.S, w.leaves, flags, 4, w.name)
+    w = workloads.c2_lognormal_zipf(scale=0.01)
+    assert_gapped_parity(w.R, w.S, w.leaves, flags, 4, w.name)
+    w = workloads.c3_dup_runs(scale=0.01)
+    assert_gapped_parity(w.R, w.S, w.leaves, flags, 4, w.name)
+
+
+@pytest.mark.parametrize("spk", [1, 2, 16])
+def test_slots_per_key(spk):
+    w = workloads.c2_lognormal_zipf(scale=0.005)
+    for flags in (lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP32 | BIN):
+        assert_gapped_parity(w.R, w.S, w.leaves, flags, spk, w.name)
+    w = workloads.c3_dup_runs(scale=0.003)
+    assert_gapped_parity(w.R, w.S, w.leaves, lj.LJ_LEAF_FP32, spk, w.name)
+
+
+@pytest.mark.parametrize("m", [1, 63, 1025, 4096 + 7, 77_777])
+@pytest.mark.parametrize("binned", [0, BIN])
+def test_ragged_tile_tails(m, binned):
+    R = workloads.gen.uniform_unique(50_000, 20, 3)
+    S = workloads.gen.probe_mix(R, m, 0.6, 4, miss_hi=2**20)
+    assert_gapped_parity(R, S, 256, lj.LJ_LEAF_FP32 | binned, 4, f"tail m={m}")
+
+
+@pytest.mark.parametrize("leaves", [1, 1000, 200_003])
+def test_leaf_counts(leaves):
+    R = workloads.gen.lognormal_unique(50_000, 2.0, 5)
+    S = workloads.gen.probe_mix(R, 60_000, 0.5, 6, miss_hi=2**63)
+    assert_gapped_parity(R, S, leaves, lj.LJ_LEAF_FP32, 4, f"leaves={leaves}")
+
+
+def test_extreme_keys_and_degenerate_relations():
+    R = np.array([0, 0, 1, 2**63, U64MAX - 1, U64MAX, U64MAX], dtype=np.uint64)
+    S = np.array([U64MAX, 0, 7, 2**63, U64MAX - 2, 1, U64MAX], dtype=np.uint64)
+    for flags in FLAGS:
+        assert_gapped_parity(R, S, 3, flags, 4, "extreme keys")
+    # UINT64_MAX absent from R: trailing gaps hold it but are no match.
+    miss = np.array([U64MAX, U64MAX - 1, U64MAX, 5, 3], dtype=np.uint64)
+    for R in ([0, 5, U64MAX - 1], [0, 5, 5, U64MAX - 1], [5], [7] * 1000):
+        for flags in (lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP32 | BIN):
+            assert_gapped_parity(R, miss, 2, flags, 4, f"n={len(R)}")
+    heavy = np.concatenate([np.arange(0, 100, dtype=np.uint64),
+                            np.full(5000, 1000, dtype=np.uint64),
+                            np.arange(2000, 2100, dtype=np.uint64)])
+    S = np.array([1000, 5, 1000, 7000, 2050, 1000], dtype=np.uint64)
+    _, got = assert_gapped_parity(heavy, S, 8, lj.LJ_LEAF_FP32, 4, "heavy duplicates")
+    assert len(got) == 3 * 5000 + 2
+
+
+@pytest.mark.parametrize("binned", [0, BIN])
+def test_empty_inputs_and_capacity(binned):
+    import torch
+    ix0 = lj.lj_build_gapped_rmi(np.empty(0, dtype=np.uint64), 4, 4, lj.LJ_LEAF_FP32 | binned)
+    assert lj.lj_self_check(ix0) == 0
+    s = lj.to_device_keys(np.array([0, 1, U64MAX], dtype=np.uint64))
+    assert lj.lj_probe_join(ix0, s) == (lj.LJ_OK, 0)
+    w = workloads.c3_dup_runs(scale=0.001)
+    want = oracle.sort_merge_join(w.R, w.S)
+    ix = lj.lj_build_gapped_rmi(w.R, w.leaves, 4, lj.LJ_LEAF_FP32 | binned)
+    s = lj.to_device_keys(w.S)
+    assert lj.lj_probe_join(ix, lj.to_device_keys(w.S[:0])) == (lj.LJ_OK, 0)
+    assert lj.lj_probe_join(ix, s, None) == (lj.LJ_OK, len(want))
+    cap = len(want) // 3
+    out = torch.full((cap, 2), -1, dtype=torch.int32, device="cuda")
+    st, cnt = lj.lj_probe_join(ix, s, out)
+    assert st == lj.LJ_ERR_CAPACITY and cnt == len(want)
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), want[:cap])
+
+
+def test_device_windows_equal_host_windows():
+    import torch
+    w = workloads.c2_lognormal_zipf(scale=0.002)
+    for flags in (lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP64):
+        host = lj.lj_build_gapped_rmi_host_only(w.R, w.leaves, 4, flags)
+        ix = lj.lj_build_gapped_rmi(w.R, w.leaves, 4, flags)
+        keys = np.concatenate([w.R, w.S])
+        want = lj.lj_predict_windows_host(host, keys)
+        assert np.array_equal(lj.lj_predict_windows_host(ix, keys)[1], want[1])
+        kd = lj.to_device_keys(keys)
+        leaf = torch.empty(len(keys), dtype=torch.int32, device="cuda")
+        got = [torch.empty(len(keys), dtype=torch.int64, device="cuda") for _ in range(3)]
+        lj.lj_predict_windows(ix, kd, leaf, *got)
+        torch.cuda.synchronize()
+        assert np.array_equal(leaf.cpu().numpy().view(np.uint32), want[0])
+        for g, h in zip(got, want[1:]):
+            assert np.array_equal(g.cpu().numpy(), h)
+
+
+@pytest.mark.parametrize("binned_min_keys", [0, 1])
+def test_batched_plan_mixes_gapped_and_plain_indexes(binned_min_keys):
+    import torch
+    ws = workloads.multi_index_batches(k=6, seed=11, n_lo=1e3, n_hi=2e5, m_lo=1, m_hi=2e5)
+    ws.append(workloads.c3_dup_runs(seed=11, scale=0.002))
+    items = []
+    for i, w in enumerate(ws):
+        flags = lj.LJ_LEAF_FP64 if i % 3 == 1 else lj.LJ_LEAF_FP32
+        ix = (lj.lj_build_gapped_rmi(w.R, w.leaves, 1 + i % 5, flags) if i % 2 == 0
+              else lj.lj_build_rmi(w.R, w.leaves, flags))
+        cap = max(1, len(w.S) * int(ix.stats.max_mult))
+        out = torch.full((cap, 2), -1, dtype=torch.int32, device="cuda")
+        cnt = torch.full((1,), -7, dtype=torch.int64, device="cuda")
+        items.append((w, ix, lj.to_device_keys(w.S), out, cnt))
+    t = lj.lj_batch_default_tuning()
+    t.binned_min_keys = binned_min_keys
+    plan = lj.BatchPlan([(ix, s, out, cnt) for _, ix, s, out, cnt in items], t)
+    for rep in range(2):
+        print(f"[gapped] plan replay {rep} binned_min_keys={binned_min_keys}", flush=True)
+        for *_, out, cnt in items:
+            out.fill_(-1)
+            cnt.fill_(-7)
+        plan.run()
+        torch.cuda.synchronize()
+        for w, _, _, out, cnt in items:
+            want = oracle.sort_merge_join(w.R, w.S)
+            n = int(cnt.item())
+            assert n == len(want)
+            assert np.array_equal(out[:n].cpu().numpy().view(np.uint32), want)
+
+
+def test_server_with_gapped_index():
+    ws = [workloads.c2_lognormal_zipf(seed=21, scale=0.002), workloads.c1_uniform(seed=22)]
+    ixs = [lj.lj_build_gapped_rmi(ws[0].R, ws[0].leaves, 4), lj.lj_build_rmi(ws[1].R, ws[1].leaves)]
+    cfg = lj.lj_server_default_config(256 << 20)
+    srv = lj.Server(ixs, cfg)
+    try:
+        tickets = []
+        rng = np.random.default_rng(5)
+        for k in range(12):
+            i = k % 2
+            a = int(rng.integers(0, len(ws[i].S) - 1000))
+            S = ws[i].S[a:a + 1 + int(rng.integers(0, 20_000))]
+            want = oracle.sort_merge_join(ws[i].R, S)
+            out = np.empty((max(1, len(want)), 2), dtype=np.uint32)
+            tickets.append((srv.submit(i, S, out), out, want))
+        for t, out, want in tickets:
+            r = srv.wait(t, 60_000)
+            assert r.status == lj.LJ_OK and r.count == len(want)
+            assert np.array_equal(out[: len(want)], want)
+    finally:
+        srv.close()
