@@ -45,11 +45,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str, binned: bool, gapped: bool = False):
+def load_traffic(workload: str, binned: bool, index: str = "rmi"):
     """HBM bytes per launch of the timed kernel from the committed rocprofv3
     counter summary, or None when absent or taken on a different kernel
     source."""
-    kind = ("probe_binned" if binned else "probe") + ("_gapped" if gapped else "")
+    kind = ("probe_binned" if binned else "probe") + ("" if index == "rmi" else "_" + index)
     path = os.path.join(ROOT, "profiles", f"{kind}_{workload}_hbm_counters.md")
     if not os.path.exists(path):
         return None
@@ -74,6 +74,8 @@ def make_workload(name: str):
         return workloads.c1_uniform()
     if name == "dup-runs-100M":
         return workloads.c3_dup_runs()
+    if name == "seq-holes-200M":
+        return workloads.c6_seq_holes()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -84,7 +86,8 @@ def algorithmic_bytes(pairs_dev, count: int, m: int, out_per_key: float = 0.0,
     insertion point, or every sector its match run spans), and its output:
     8 B per emitted pair (fused probe), or out_per_key bytes of per-key
     result (search kernel of the binned probe).  The searched array is R
-    (8 B per key) or a gapped RMI's slots (slot_bytes = 16).  Computed from
+    (8 B per key), a gapped RMI's slots or a learned hash's buckets (16 B
+    per key of R: slot_bytes = 16).  Computed from
     the emitted pairs: a key with matches owns one contiguous run of r
     indices, and of slots."""
     import torch
@@ -346,10 +349,11 @@ def main():
                     help="last-mile search inside the error bounds")
     ap.add_argument("--probe", choices=["direct", "binned"], default="binned",
                     help="probe S in its own order, or partitioned by key range first")
-    ap.add_argument("--index", choices=["rmi", "gapped"], default="rmi",
-                    help="plain RMI over R, or gapped RMI (model-based insertion)")
+    ap.add_argument("--index", choices=["rmi", "gapped", "hash"], default="rmi",
+                    help="plain RMI over R, gapped RMI (model-based insertion), or "
+                         "learned hash (the RMI as hash function of a bucket-chained table)")
     ap.add_argument("--slots-per-key", type=int, default=4,
-                    help="gapped RMI: slots of the gapped arrays per key of R")
+                    help="gapped RMI or learned hash: slots per key of R")
     ap.add_argument("--cpu-sample", type=int, default=120_000_000,
                     help="outer keys in the timed oracle sample (0 = skip)")
     ap.add_argument("--requests", type=int, default=1000,
@@ -387,9 +391,12 @@ def main():
         flags |= lj.LJ_PROBE_BINNED
     stream = torch.cuda.current_stream()
     gapped = args.index == "gapped"
+    hashed = args.index == "hash"
     t0 = time.perf_counter()
     if gapped:
         ix = lj.lj_build_gapped_rmi(w.R, w.leaves, args.slots_per_key, flags, stream)
+    elif hashed:
+        ix = lj.lj_build_learned_hash(w.R, w.leaves, args.slots_per_key, flags, stream)
     else:
         ix = lj.lj_build_rmi(w.R, w.leaves, flags, stream)
     build_s = time.perf_counter() - t0
@@ -437,7 +444,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    slot_bytes = 16 if gapped else 8
+    slot_bytes = 16 if gapped or hashed else 8
     if binned:  # search kernel: keys in, one 4-byte (8 with duplicates) result out
         alg = algorithmic_bytes(out, int(count), m, 4.0 if st.max_mult <= 1 else 8.0, 0.0,
                                 slot_bytes)
@@ -446,7 +453,7 @@ def main():
     achieved = alg / (kern_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": load_traffic(w.name, binned, gapped),
+            "traffic": load_traffic(w.name, binned, args.index),
             "algorithmic_bytes_per_launch": alg,
             "kernel": "probe_binned_kernel" if binned else "probe_join_kernel",
             "kernel_ms": round(kern_ms, 4)}
@@ -468,10 +475,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": len(w.R), "m": m, "leaves": w.leaves,
                    "leaf_model": args.leaf,
-                   "search": "gapped-exponential" if gapped else args.search,
+                   "search": ("gapped-exponential" if gapped else "bucket-chain" if hashed
+                              else args.search),
                    "probe": args.probe,
                    "index": args.index,
-                   "slots_per_key": args.slots_per_key if gapped else None,
+                   "slots_per_key": args.slots_per_key if gapped or hashed else None,
                    "pairs": int(count),
                    "mean_window": round(st.mean_window, 2), "max_window": int(st.max_window)},
         "roofline": roof,

@@ -126,6 +126,30 @@ int lj_build_gapped_rmi(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves
                         uint32_t slots_per_key, uint32_t flags, hipStream_t stream,
                         lj_index** out_index);
 
+/*
+ * Build a learned hash index (Section III-C, "Learned-based Hash INLJ"):
+ * the same two-level RMI serves as an order-preserving hash function into a
+ * bucket-chained table; nothing is searched.  The bucket of a key is its
+ * predicted position in R (clamped into its leaf's run) times
+ * slots_per_key / 4, so there are about slots_per_key * n / 4 primary
+ * buckets of 4 slots (64 bytes: 4 keys, their positions in R, the next
+ * bucket of the chain, the number of keys held).  Keys of R are appended to
+ * their chain in R order, so all copies of a key share one chain, in
+ * order.  A probe walks the chain of its key's bucket; every entry point
+ * that takes an index works on it and emits the same pairs as for a plain
+ * RMI.
+ *
+ *   slots_per_key  1..16 (4: one bucket of 4 slots per key of R, the
+ *                  bucket size and load factor of the evaluation's hash
+ *                  baseline).  Device memory: 64 bytes per bucket,
+ *                  overflow buckets included, on top of R and the leaves.
+ *
+ * Other arguments and errors as lj_build_gapped_rmi.
+ */
+int lj_build_learned_hash(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves,
+                          uint32_t slots_per_key, uint32_t flags, hipStream_t stream,
+                          lj_index** out_index);
+
 /* Release an index and its device memory.  NULL is ignored.  The caller
  * must ensure no probe of this index is still running on any stream. */
 void lj_free_index(lj_index* index);
@@ -370,14 +394,18 @@ typedef struct {
     uint32_t max_leaf_keys;   /* keys in the largest leaf */
     uint64_t max_mult;        /* longest run of equal keys in R */
     double mean_window;       /* mean search-window length over the keys of R
-                                 (in slots for a gapped RMI) */
+                                 (in slots for a gapped RMI; for a learned
+                                 hash, the mean number of buckets a probe of
+                                 a key of R reads) */
     uint64_t max_window;      /* largest search window of any leaf */
     uint64_t device_bytes;    /* device memory held (R + leaf table) */
     double root_a0, root_b0;  /* root model parameters */
     uint64_t root_kmin;       /* root model key origin (R[0]) */
-    uint32_t slots_per_key;   /* gapped RMI: slots per key of R (0: plain RMI) */
+    uint32_t slots_per_key;   /* gapped RMI or learned hash: slots per key of R
+                                 (0: plain RMI) */
     uint32_t pad;
-    uint64_t nslots;          /* gapped RMI: slots of the gapped arrays */
+    uint64_t nslots;          /* gapped RMI: slots of the gapped arrays;
+                                 learned hash: 4 per bucket, overflow included */
 } lj_index_stats;
 
 int lj_index_get_stats(const lj_index* index, lj_index_stats* out);
@@ -388,7 +416,9 @@ int lj_index_get_stats(const lj_index* index, lj_index_stats* out);
  * their search window (0 means the host-built bounds hold on the device);
  * for a gapped RMI, every key slot whose key differs from R at its payload
  * position or lies outside its slot window, plus the difference between
- * the number of key slots and n.
+ * the number of key slots and n; for a learned hash, every key of R not
+ * found in the chain of its bucket, plus the difference between the number
+ * of keys the buckets hold and n.
  * Synchronous.  Errors: LJ_ERR_ARG, LJ_ERR_DEVICE, LJ_ERR_OOM.
  */
 int lj_self_check(const lj_index* index, uint64_t* out_violations_host,
@@ -398,7 +428,9 @@ int lj_self_check(const lj_index* index, uint64_t* out_violations_host,
  * Window diagnostics: for each of m keys (device memory), the leaf chosen by
  * the root, the predicted absolute position (-1 for an empty leaf) and the
  * absolute search window [lo, hi] the probe searches (lo > hi = empty
- * window); for a gapped RMI the predicted slot and the slot window.  Used by tests and for model-quality statistics; not part of the
+ * window); for a gapped RMI the predicted slot and the slot window; for a
+ * learned hash the primary bucket (pred = lo = hi).  Used by tests and for
+ * model-quality statistics; not part of the
  * join.  Any output pointer may be NULL.  Asynchronous on `stream`.
  */
 int lj_predict_windows(const lj_index* index, const uint64_t* keys_dev,
@@ -443,6 +475,27 @@ int lj_build_gapped_rmi_host_only(const uint64_t* r_keys_host, uint64_t n,
 int lj_gapped_slots_host(const lj_index* index, uint64_t* keys_host,
                          uint32_t* ridx_host, uint64_t capacity,
                          uint64_t* nslots_out);
+
+/* Host-only build of a learned hash index (arguments as
+ * lj_build_learned_hash); its buckets can be read with lj_hash_buckets_host. */
+int lj_build_learned_hash_host_only(const uint64_t* r_keys_host, uint64_t n,
+                                    uint32_t leaves, uint32_t slots_per_key,
+                                    uint32_t flags, lj_index** out_index);
+
+/*
+ * Copy the buckets of a host-only learned hash index: for bucket b <
+ * capacity, keys_host[4b + j] and ridx_host[4b + j] for its slots j < 4
+ * (key 0 and UINT32_MAX for an empty slot) and next_host[b] (the next
+ * bucket of the chain, UINT32_MAX at the end).  Buckets [0, *nprimary_out)
+ * are the primary ones; *nbuckets_out receives the number of buckets.
+ * nprimary_out may be NULL.  Errors: LJ_ERR_ARG (not a host-only learned
+ * hash index), LJ_ERR_CAPACITY (capacity below the bucket count; the first
+ * buckets are copied).
+ */
+int lj_hash_buckets_host(const lj_index* index, uint64_t* keys_host,
+                         uint32_t* ridx_host, uint32_t* next_host,
+                         uint64_t capacity, uint64_t* nbuckets_out,
+                         uint64_t* nprimary_out);
 
 /*
  * Timing hook for benchmarks: the next lj_probe_join or lj_probe_join_async

@@ -58,10 +58,12 @@ int validate_build(const uint64_t* r, uint64_t n, uint32_t leaves, uint32_t flag
     return LJ_OK;
 }
 
-// gap_factor 0: plain RMI; otherwise a gapped RMI with that many slots per
-// key of R.
-int build_common(const uint64_t* r, uint64_t n, uint32_t leaves, uint32_t flags,
-                 uint32_t gap_factor, lj_index** out) {
+// What is built over the RMI: nothing (a plain RMI), gapped arrays or a
+// learned hash table, with that many slots per key of R.
+enum class Extra { kNone, kGapped, kHash };
+
+int build_common(const uint64_t* r, uint64_t n, uint32_t leaves, uint32_t flags, Extra extra,
+                 uint32_t slots_per_key, lj_index** out) {
     if (!out) return LJ_ERR_ARG;
     *out = nullptr;
     int st = validate_build(r, n, leaves, flags);
@@ -70,7 +72,8 @@ int build_common(const uint64_t* r, uint64_t n, uint32_t leaves, uint32_t flags,
     if (!idx) return LJ_ERR_OOM;
     try {
         st = lj::fit_rmi(r, n, leaves, flags, idx);
-        if (st == LJ_OK && gap_factor) st = lj::fit_gapped(r, gap_factor, idx);
+        if (st == LJ_OK && extra == Extra::kGapped) st = lj::fit_gapped(r, slots_per_key, idx);
+        if (st == LJ_OK && extra == Extra::kHash) st = lj::fit_hash(r, slots_per_key, idx);
     } catch (const std::bad_alloc&) {
         st = LJ_ERR_OOM;
     }
@@ -83,7 +86,8 @@ int build_common(const uint64_t* r, uint64_t n, uint32_t leaves, uint32_t flags,
 }
 
 int build_device(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves, uint32_t flags,
-                 uint32_t gap_factor, hipStream_t stream, lj_index** out_index);
+                 Extra extra, uint32_t slots_per_key, hipStream_t stream,
+                 lj_index** out_index);
 
 }  // namespace
 
@@ -91,7 +95,7 @@ extern "C" {
 
 int lj_build_rmi_host_only(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves,
                            uint32_t flags, lj_index** out_index) {
-    int st = build_common(r_keys_host, n, leaves, flags, 0, out_index);
+    int st = build_common(r_keys_host, n, leaves, flags, Extra::kNone, 0, out_index);
     if (st == LJ_OK) (*out_index)->host_only = true;
     return st;
 }
@@ -101,14 +105,26 @@ int lj_build_gapped_rmi_host_only(const uint64_t* r_keys_host, uint64_t n, uint3
                                   lj_index** out_index) {
     if (out_index) *out_index = nullptr;
     if (slots_per_key < 1 || slots_per_key > kMaxSlotsPerKey) return LJ_ERR_ARG;
-    int st = build_common(r_keys_host, n, leaves, flags, slots_per_key, out_index);
+    int st = build_common(r_keys_host, n, leaves, flags, Extra::kGapped, slots_per_key,
+                          out_index);
+    if (st == LJ_OK) (*out_index)->host_only = true;
+    return st;
+}
+
+int lj_build_learned_hash_host_only(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves,
+                                    uint32_t slots_per_key, uint32_t flags,
+                                    lj_index** out_index) {
+    if (out_index) *out_index = nullptr;
+    if (slots_per_key < 1 || slots_per_key > kMaxSlotsPerKey) return LJ_ERR_ARG;
+    int st = build_common(r_keys_host, n, leaves, flags, Extra::kHash, slots_per_key,
+                          out_index);
     if (st == LJ_OK) (*out_index)->host_only = true;
     return st;
 }
 
 int lj_build_rmi(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves, uint32_t flags,
                  hipStream_t stream, lj_index** out_index) {
-    return build_device(r_keys_host, n, leaves, flags, 0, stream, out_index);
+    return build_device(r_keys_host, n, leaves, flags, Extra::kNone, 0, stream, out_index);
 }
 
 int lj_build_gapped_rmi(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves,
@@ -116,7 +132,17 @@ int lj_build_gapped_rmi(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves
                         lj_index** out_index) {
     if (out_index) *out_index = nullptr;
     if (slots_per_key < 1 || slots_per_key > kMaxSlotsPerKey) return LJ_ERR_ARG;
-    return build_device(r_keys_host, n, leaves, flags, slots_per_key, stream, out_index);
+    return build_device(r_keys_host, n, leaves, flags, Extra::kGapped, slots_per_key, stream,
+                        out_index);
+}
+
+int lj_build_learned_hash(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves,
+                          uint32_t slots_per_key, uint32_t flags, hipStream_t stream,
+                          lj_index** out_index) {
+    if (out_index) *out_index = nullptr;
+    if (slots_per_key < 1 || slots_per_key > kMaxSlotsPerKey) return LJ_ERR_ARG;
+    return build_device(r_keys_host, n, leaves, flags, Extra::kHash, slots_per_key, stream,
+                        out_index);
 }
 
 }  // extern "C"
@@ -124,8 +150,9 @@ int lj_build_gapped_rmi(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves
 namespace {
 
 int build_device(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves, uint32_t flags,
-                 uint32_t gap_factor, hipStream_t stream, lj_index** out_index) {
-    int st = build_common(r_keys_host, n, leaves, flags, gap_factor, out_index);
+                 Extra extra, uint32_t slots_per_key, hipStream_t stream,
+                 lj_index** out_index) {
+    int st = build_common(r_keys_host, n, leaves, flags, extra, slots_per_key, out_index);
     if (st != LJ_OK) return st;
     lj_index* idx = *out_index;
     *out_index = nullptr;
@@ -141,16 +168,18 @@ int build_device(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves, uint3
     const uint64_t fbytes = idx->fences.size() * sizeof(uint64_t);
     const uint64_t bbytes = idx->bucket_lo.size() * sizeof(uint16_t);
     const uint64_t sbytes = idx->slots.size() * sizeof(lj::GSlot);
+    const uint64_t hbytes = idx->buckets.size() * sizeof(lj::HBucket);
     if (hipMalloc((void**)&idx->r_dev, rbytes) != hipSuccess ||
         hipMalloc(&idx->leaf_dev, lbytes) != hipSuccess ||
         (fbytes && hipMalloc((void**)&idx->fences_dev, fbytes) != hipSuccess) ||
         (bbytes && hipMalloc((void**)&idx->bucket_lo_dev, bbytes) != hipSuccess) ||
-        (sbytes && hipMalloc((void**)&idx->slots_dev, sbytes) != hipSuccess)) {
+        (sbytes && hipMalloc((void**)&idx->slots_dev, sbytes) != hipSuccess) ||
+        (hbytes && hipMalloc((void**)&idx->buckets_dev, hbytes) != hipSuccess)) {
         (void)hipGetLastError();
         lj_free_index(idx);
         return LJ_ERR_OOM;
     }
-    idx->device_bytes = rbytes + lbytes + fbytes + bbytes + sbytes;
+    idx->device_bytes = rbytes + lbytes + fbytes + bbytes + sbytes + hbytes;
     hipError_t e = hipSuccess;
     if (n) e = hipMemcpyAsync(idx->r_dev, r_keys_host, n * sizeof(uint64_t),
                               hipMemcpyHostToDevice, stream);
@@ -165,12 +194,16 @@ int build_device(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves, uint3
     if (e == hipSuccess && sbytes)
         e = hipMemcpyAsync(idx->slots_dev, idx->slots.data(), sbytes, hipMemcpyHostToDevice,
                            stream);
+    if (e == hipSuccess && hbytes)
+        e = hipMemcpyAsync(idx->buckets_dev, idx->buckets.data(), hbytes, hipMemcpyHostToDevice,
+                           stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
         lj_free_index(idx);
         return LJ_ERR_DEVICE;
     }
-    std::vector<lj::GSlot>().swap(idx->slots);  // the device copy is the one probed
+    std::vector<lj::GSlot>().swap(idx->slots);  // the device copies are the ones probed
+    std::vector<lj::HBucket>().swap(idx->buckets);
     *out_index = idx;
     return LJ_OK;
 }
@@ -186,6 +219,7 @@ void lj_free_index(lj_index* idx) {
     if (idx->fences_dev) (void)hipFree(idx->fences_dev);
     if (idx->bucket_lo_dev) (void)hipFree(idx->bucket_lo_dev);
     if (idx->slots_dev) (void)hipFree(idx->slots_dev);
+    if (idx->buckets_dev) (void)hipFree(idx->buckets_dev);
     delete idx;
 }
 
@@ -287,9 +321,9 @@ int lj_index_get_stats(const lj_index* idx, lj_index_stats* o) {
     o->root_a0 = idx->root.a0;
     o->root_b0 = idx->root.b0;
     o->root_kmin = idx->root.kmin;
-    o->slots_per_key = idx->gap;
+    o->slots_per_key = idx->gap ? idx->gap : idx->hash_spk;
     o->pad = 0;
-    o->nslots = idx->nslots;
+    o->nslots = idx->gap ? idx->nslots : idx->nbuckets * lj::kBucketSlots;
     return LJ_OK;
 }
 
@@ -304,6 +338,25 @@ int lj_gapped_slots_host(const lj_index* idx, uint64_t* keys, uint32_t* ridx, ui
         ridx[j] = idx->slots[j].ridx;
     }
     return cap >= idx->nslots ? LJ_OK : LJ_ERR_CAPACITY;
+}
+
+int lj_hash_buckets_host(const lj_index* idx, uint64_t* keys, uint32_t* ridx, uint32_t* next,
+                         uint64_t cap, uint64_t* nbuckets_out, uint64_t* nprimary_out) {
+    if (!idx || !idx->hash_spk || idx->buckets.size() != idx->nbuckets || !nbuckets_out)
+        return LJ_ERR_ARG;
+    if (cap && (!keys || !ridx || !next)) return LJ_ERR_ARG;
+    *nbuckets_out = idx->nbuckets;
+    if (nprimary_out) *nprimary_out = idx->nprimary;
+    const uint64_t k = std::min<uint64_t>(cap, idx->nbuckets);
+    for (uint64_t b = 0; b < k; ++b) {
+        const lj::HBucket& h = idx->buckets[b];
+        for (uint32_t j = 0; j < lj::kBucketSlots; ++j) {
+            keys[b * lj::kBucketSlots + j] = j < h.nkeys ? h.key[j] : 0;
+            ridx[b * lj::kBucketSlots + j] = j < h.nkeys ? h.ridx[j] : lj::kGap;
+        }
+        next[b] = h.next;
+    }
+    return cap >= idx->nbuckets ? LJ_OK : LJ_ERR_CAPACITY;
 }
 
 int lj_self_check(const lj_index* idx, uint64_t* viol_host, hipStream_t stream) {
@@ -354,7 +407,12 @@ int lj_predict_windows_host(const lj_index* idx, const uint64_t* keys, uint64_t 
             elo = lf.lo;
             ehi = lf.hi;
         }
-        if (cnt && idx->gap) {
+        if (cnt && idx->hash_spk) {
+            // Learned hash: the primary bucket.
+            int64_t rc = rel < 0 ? 0 : (rel > (int64_t)cnt - 1 ? (int64_t)cnt - 1 : rel);
+            pr = (((int64_t)pos0 + rc) * (int64_t)idx->hash_spk) / (int64_t)lj::kBucketSlots;
+            lo = hi = pr;
+        } else if (cnt && idx->gap) {
             // Gapped index: slot window [s, s + hi] of the predicted slot s.
             int64_t rc = rel < 0 ? 0 : (rel > (int64_t)cnt - 1 ? (int64_t)cnt - 1 : rel);
             pr = ((int64_t)pos0 + rc) * (int64_t)idx->gap;

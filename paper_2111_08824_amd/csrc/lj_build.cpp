@@ -250,7 +250,63 @@ int fit_gapped_leaves(const uint64_t* r, uint32_t G, std::vector<Leaf>& lv, lj_i
     return LJ_OK;
 }
 
+// Learned hash table for one leaf arithmetic (Section III-C): the RMI's
+// position estimate is the hash; keys of R go, in order, to the end of
+// their bucket's chain, so each chain lists its keys in R order and all
+// copies of a key share one chain.
+template <class Leaf>
+int fit_hash_leaves(const uint64_t* r, uint32_t spk, const std::vector<Leaf>& lv,
+                    lj_index* idx) {
+    const uint64_t n = idx->n;
+    const uint64_t nprimary = n ? ((n - 1) * spk) / kBucketSlots + 1 : 1;
+    if (nprimary >= kNoBucket) return LJ_ERR_TOO_LARGE;
+    std::vector<uint64_t> bucket(n);
+    parallel_items(lv.size(), [&](uint64_t l) {
+        const Leaf& lf = lv[l];
+        for (uint64_t i = lf.pos0; i < (uint64_t)lf.pos0 + lf.cnt; ++i)
+            bucket[i] = hash_bucket(lf, r[i], spk);
+    });
+    std::vector<HBucket>& B = idx->buckets;
+    B.assign(nprimary, HBucket{{0, 0, 0, 0}, {kGap, kGap, kGap, kGap}, kNoBucket, 0u, {0u, 0u}});
+    std::vector<uint32_t> tail(nprimary);
+    for (uint64_t b = 0; b < nprimary; ++b) tail[b] = (uint32_t)b;
+    double depth_sum = 0;
+    uint64_t depth_max = 0;
+    std::vector<uint32_t> depth(nprimary, 1);  // chain length of each primary bucket
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t b = bucket[i];
+        uint32_t t = tail[b];
+        if (B[t].nkeys == kBucketSlots) {
+            if (B.size() >= kNoBucket) return LJ_ERR_TOO_LARGE;
+            const uint32_t nb = (uint32_t)B.size();
+            B.push_back(HBucket{{0, 0, 0, 0}, {kGap, kGap, kGap, kGap}, kNoBucket, 0u, {0u, 0u}});
+            B[t].next = nb;
+            tail[b] = t = nb;
+            ++depth[b];
+        }
+        HBucket& h = B[t];
+        h.key[h.nkeys] = r[i];
+        h.ridx[h.nkeys] = (uint32_t)i;
+        ++h.nkeys;
+        depth_sum += depth[b];
+        depth_max = std::max<uint64_t>(depth_max, depth[b]);
+    }
+    idx->nprimary = nprimary;
+    idx->nbuckets = B.size();
+    idx->hash_spk = spk;
+    // Window statistics in buckets: chain position of each key of R.
+    idx->mean_window = n ? depth_sum / (double)n : 0.0;
+    idx->max_window = depth_max;
+    return LJ_OK;
+}
+
 }  // namespace
+
+int fit_hash(const uint64_t* r, uint32_t spk, lj_index* idx) {
+    if (spk < 1) return LJ_ERR_ARG;
+    return leaf_fp32(idx->flags) ? fit_hash_leaves(r, spk, idx->leaf32, idx)
+                                 : fit_hash_leaves(r, spk, idx->leaf64, idx);
+}
 
 int fit_gapped(const uint64_t* r, uint32_t G, lj_index* idx) {
     if (G < 1) return LJ_ERR_ARG;

@@ -22,6 +22,20 @@ struct alignas(16) GSlot {
 };
 constexpr uint32_t kGap = 0xFFFFFFFFu;
 
+// Bucket of the learned hash index (Section III-C, "Learned-based Hash
+// INLJ"): up to four keys of R with their positions, the number of keys
+// held and the next bucket of the chain (kNoBucket at the end); one 64-byte
+// line, read with four 16-byte loads.
+struct alignas(64) HBucket {
+    uint64_t key[4];
+    uint32_t ridx[4];
+    uint32_t next;
+    uint32_t nkeys;
+    uint32_t pad[2];
+};
+constexpr uint32_t kBucketSlots = 4;
+constexpr uint32_t kNoBucket = 0xFFFFFFFFu;
+
 }  // namespace lj
 
 struct lj_index {
@@ -57,6 +71,16 @@ struct lj_index {
     std::vector<lj::GSlot> slots;
     lj::GSlot* slots_dev = nullptr;
 
+    // Learned hash index: slots per key of R (0 for none; buckets of four
+    // slots), primary buckets (one per bucket value of the hash), all
+    // buckets (primary, then overflow), the bucket array (host copy kept
+    // for host-only indexes).
+    uint32_t hash_spk = 0;
+    uint64_t nprimary = 0;
+    uint64_t nbuckets = 0;
+    std::vector<lj::HBucket> buckets;
+    lj::HBucket* buckets_dev = nullptr;
+
     // device copies
     uint64_t* r_dev = nullptr;
     void* leaf_dev = nullptr;
@@ -78,6 +102,22 @@ int fit_rmi(const uint64_t* r, uint64_t n, uint32_t leaves, uint32_t flags,
 // insertion of R into the slot array and per-leaf slot bounds (host only).
 int fit_gapped(const uint64_t* r, uint32_t G, lj_index* idx);
 
+// Build the learned hash index over a fitted RMI: every key of R, in order,
+// appended to the chain of its bucket (host only).
+int fit_hash(const uint64_t* r, uint32_t slots_per_key, lj_index* idx);
+
+// Bucket of key x in a learned hash index: the leaf's predicted position,
+// clamped into the leaf's run, times slots_per_key / kBucketSlots (the
+// model's CDF estimate scaled to the primary buckets).  The leaf must not
+// be empty.
+template <class Leaf>
+__host__ __device__ inline uint64_t hash_bucket(const Leaf& lf, uint64_t x, uint32_t spk) {
+    int64_t rel = predict_rel(lf, x);
+    if (rel < 0) rel = 0;
+    if (rel > (int64_t)lf.cnt - 1) rel = (int64_t)lf.cnt - 1;
+    return (((uint64_t)lf.pos0 + (uint64_t)rel) * spk) / kBucketSlots;
+}
+
 // Predicted slot of key x in a gapped index: the leaf's predicted position,
 // clamped into the leaf's run, times G.  The leaf must not be empty.
 template <class Leaf>
@@ -97,6 +137,7 @@ constexpr int kBlock = 256;
 constexpr int kItemsUnique = 24;
 constexpr int kItemsDup = 16;
 constexpr int kItemsGapped = 8;
+constexpr int kItemsHash = 8;  // learned hash index: a 64-byte bucket in flight per key
 constexpr int kItemsBinned = 16;  // search kernel of the binned probe (measured best)
 constexpr int kSetupChunk = 4;
 constexpr int kMinTile = kBlock * 4;  // smallest tile any launch uses
@@ -218,21 +259,24 @@ struct TileJob {
     uint32_t* done;        // tiles of this batch finished
     uint32_t* err;         // error flag shared by the launch
     uint32_t ntiles;
-    uint32_t kind;         // kJobFp64 | kJobDup | kJobExp | kJobGapped
+    uint32_t kind;         // kJobFp64 | kJobDup | kJobExp | kJobGapped | kJobHash
     uint32_t kpl;          // keys per lane in this batch's tiles
     const GSlot* slots;    // gapped index: slot array, its size and gap factor
     uint32_t nslots;
     uint32_t gap;
+    const HBucket* buckets;  // learned hash index: buckets, slots per key
+    uint32_t hash_spk;
 };
 constexpr uint32_t kJobFp64 = 1u;
 constexpr uint32_t kJobDup = 2u;
 constexpr uint32_t kJobExp = 4u;
 constexpr uint32_t kJobGapped = 8u;
+constexpr uint32_t kJobHash = 16u;
 
 inline uint32_t job_kind(const lj_index* idx) {
     return ((idx->flags & LJ_LEAF_FP64) ? kJobFp64 : 0u) | (idx->max_mult > 1 ? kJobDup : 0u) |
            ((idx->flags & LJ_SEARCH_EXPONENTIAL) ? kJobExp : 0u) |
-           (idx->gap ? kJobGapped : 0u);
+           (idx->gap ? kJobGapped : 0u) | (idx->hash_spk ? kJobHash : 0u);
 }
 
 // Kernel launchers (lj_kernels.hip).  Return hipSuccess or the launch error.

@@ -442,6 +442,76 @@ __device__ __forceinline__ void search_keys_gapped(const GSlot* __restrict__ slo
     }
 }
 
+// Steps 1-4 on a learned hash index (Section III-C) for the keys of one
+// tile (layout as in search_keys): root model, leaf model, bucket of the
+// key, then a lockstep walk of each key's bucket chain, one 64-byte bucket
+// per step, counting the slots that hold x.  Keys of R sit in their chain
+// in R order, so the first match is the first copy of x.  A key stops at
+// its first match when R has no duplicates, else at the end of its chain.
+template <class Leaf, bool kUnique, int kItems>
+__device__ __forceinline__ void search_keys_hash(const HBucket* __restrict__ buckets,
+                                                 const uint32_t spk, const Leaf* leaves,
+                                                 const RootModel& root, const uint64_t* s,
+                                                 const uint64_t m, const uint64_t tbase,
+                                                 const uint32_t kpl, uint32_t (&first)[kItems],
+                                                 uint32_t (&c)[kItems]) {
+    const int tid = threadIdx.x;
+    uint64_t x[kItems];
+    uint32_t cur[kItems];  // bucket to read next, or kNoBucket
+    uint32_t validmask = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const uint64_t q = tbase + (uint64_t)k * kBlock + tid;
+        const bool ok = (uint32_t)k < kpl && q < m;
+        validmask |= (ok ? 1u : 0u) << k;
+        x[k] = s[ok ? q : m - 1];
+    }
+#pragma unroll
+    for (int k0 = 0; k0 < kItems; k0 += kSetupChunk) {
+        Leaf lf[kSetupChunk];
+#pragma unroll
+        for (int u = 0; u < kSetupChunk; ++u) lf[u] = load_leaf(leaves + route(root, x[k0 + u]));
+#pragma unroll
+        for (int u = 0; u < kSetupChunk; ++u) {
+            const int k = k0 + u;
+            const bool live = ((validmask >> k) & 1u) && lf[u].cnt != 0;
+            cur[k] = live ? (uint32_t)hash_bucket(lf[u], x[k], spk) : kNoBucket;
+            first[k] = 0;
+            c[k] = 0;
+        }
+    }
+    for (;;) {
+        uint32_t any = 0;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) any |= cur[k] != kNoBucket ? 1u : 0u;
+        if (!any) break;
+        uint4 v[kItems][4];
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const uint4* p = (const uint4*)(buckets + (cur[k] != kNoBucket ? cur[k] : 0u));
+#pragma unroll
+            for (int w = 0; w < 4; ++w) v[k][w] = p[w];
+        }
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const bool act = cur[k] != kNoBucket;
+            const uint32_t nk = v[k][3].y;
+            const uint64_t key[4] = {(uint64_t)v[k][0].x | ((uint64_t)v[k][0].y << 32),
+                                     (uint64_t)v[k][0].z | ((uint64_t)v[k][0].w << 32),
+                                     (uint64_t)v[k][1].x | ((uint64_t)v[k][1].y << 32),
+                                     (uint64_t)v[k][1].z | ((uint64_t)v[k][1].w << 32)};
+            const uint32_t rid[4] = {v[k][2].x, v[k][2].y, v[k][2].z, v[k][2].w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t hit = act && (uint32_t)j < nk && key[j] == x[k] ? 1u : 0u;
+                first[k] = hit && c[k] == 0 ? rid[j] : first[k];
+                c[k] += hit;
+            }
+            cur[k] = !act || (kUnique && c[k] != 0) ? kNoBucket : v[k][3].x;
+        }
+    }
+}
+
 // Steps 5-7 for one tile whose lower bounds and run lengths are known:
 // offsets, look-back, pair emission; then the tile is counted as done.
 // Without kLookBack the tile's output offset is given (excl_given) and the
@@ -568,6 +638,7 @@ __device__ __forceinline__ void emit_tile(const TileJob& j, const uint32_t tile,
 constexpr int kSearchBinary = 0;
 constexpr int kSearchExp = 1;
 constexpr int kSearchGapped = 2;
+constexpr int kSearchHash = 3;
 
 // Probe one tile of a batch (steps 1-7).
 template <class Leaf, bool kUnique, int kItems, bool kWithOffsets, int kSearch>
@@ -575,7 +646,11 @@ __device__ __forceinline__ void probe_tile(const TileJob& j, const uint32_t tile
                                            const uint32_t kpl,
                                            TileShared<kItems, kWithOffsets>& sh) {
     uint32_t first[kItems], c[kItems];
-    if constexpr (kSearch == kSearchGapped)
+    if constexpr (kSearch == kSearchHash)
+        search_keys_hash<Leaf, kUnique, kItems>(j.buckets, j.hash_spk, (const Leaf*)j.leaves,
+                                                j.root, j.s, j.m, (uint64_t)tile * kBlock * kpl,
+                                                kpl, first, c);
+    else if constexpr (kSearch == kSearchGapped)
         search_keys_gapped<Leaf, kUnique, kItems>(j.slots, j.nslots, j.gap,
                                                   (const Leaf*)j.leaves, j.root, j.s, j.m,
                                                   (uint64_t)tile * kBlock * kpl, kpl, first, c);
@@ -605,14 +680,18 @@ __global__ __launch_bounds__(kBlock) void probe_join_kernel(TileJob j, uint32_t*
 template <class Leaf, bool kUnique, int kItems, int kSearch>
 __global__ __launch_bounds__(kBlock) void probe_binned_kernel(
     const uint64_t* __restrict__ R, const Leaf* leaves, RootModel root,
-    const GSlot* __restrict__ slots, uint32_t nslots, uint32_t G, const uint64_t* keys,
+    const GSlot* __restrict__ slots, uint32_t nslots, uint32_t G,
+    const HBucket* __restrict__ buckets, uint32_t hash_spk, const uint64_t* keys,
     uint64_t m, uint32_t ntiles, uint32_t tiles_per_xcd, void* res) {
     const uint32_t slot = blockIdx.x / kXcds;
     const uint32_t tile = (blockIdx.x % kXcds) * tiles_per_xcd + slot;
     if (slot >= tiles_per_xcd || tile >= ntiles) return;
     const uint64_t tbase = (uint64_t)tile * kBlock * kItems;
     uint32_t first[kItems], c[kItems];
-    if constexpr (kSearch == kSearchGapped)
+    if constexpr (kSearch == kSearchHash)
+        search_keys_hash<Leaf, kUnique, kItems>(buckets, hash_spk, leaves, root, keys, m, tbase,
+                                                kItems, first, c);
+    else if constexpr (kSearch == kSearchGapped)
         search_keys_gapped<Leaf, kUnique, kItems>(slots, nslots, G, leaves, root, keys, m, tbase,
                                                   kItems, first, c);
     else
@@ -838,6 +917,42 @@ __global__ void self_check_gapped_kernel(const uint64_t* R, uint64_t n, const GS
     if (keys) atomicAdd(nkeys, (unsigned long long)keys);
 }
 
+// Learned hash index: every key of R must be found, with its own position,
+// in the chain of its bucket (a chain longer than nbuckets is a violation,
+// not a hang); bucket_keys_kernel counts the keys the buckets hold.
+template <class Leaf>
+__global__ void self_check_hash_kernel(const uint64_t* R, uint64_t n, const HBucket* buckets,
+                                       uint64_t nbuckets, uint32_t spk, const Leaf* leaves,
+                                       RootModel root, unsigned long long* viol) {
+    uint32_t bad = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t x = R[i];
+        const Leaf lf = leaves[route(root, x)];
+        bool found = false;
+        if (lf.cnt != 0) {
+            uint64_t b = hash_bucket(lf, x, spk);
+            for (uint64_t hops = 0; b < nbuckets && hops < nbuckets && !found; ++hops) {
+                const HBucket& h = buckets[b];
+                for (uint32_t j = 0; j < kBucketSlots && j < h.nkeys; ++j)
+                    found = found || (h.ridx[j] == (uint32_t)i && h.key[j] == x);
+                b = h.next;
+            }
+        }
+        bad += found ? 0u : 1u;
+    }
+    if (bad) atomicAdd(viol, (unsigned long long)bad);
+}
+
+__global__ void bucket_keys_kernel(const HBucket* buckets, uint64_t nbuckets,
+                                   unsigned long long* nkeys) {
+    uint32_t keys = 0;
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nbuckets;
+         b += (uint64_t)gridDim.x * blockDim.x)
+        keys += buckets[b].nkeys;
+    if (keys) atomicAdd(nkeys, (unsigned long long)keys);
+}
+
 // viol[0] += |nkeys - n|.
 __global__ void finish_gapped_check_kernel(unsigned long long* viol, const unsigned long long* nkeys,
                                            uint64_t n) {
@@ -848,15 +963,18 @@ __global__ void finish_gapped_check_kernel(unsigned long long* viol, const unsig
 template <class Leaf>
 __global__ void predict_windows_kernel(const uint64_t* keys, uint64_t m, const Leaf* leaves,
                                        RootModel root, uint32_t G, uint64_t nslots,
-                                       uint32_t* leaf_out, int64_t* pred, int64_t* wlo,
-                                       int64_t* whi) {
+                                       uint32_t hash_spk, uint32_t* leaf_out, int64_t* pred,
+                                       int64_t* wlo, int64_t* whi) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
          i += (uint64_t)gridDim.x * blockDim.x) {
         uint64_t x = keys[i];
         uint32_t l = route(root, x);
         const Leaf lf = leaves[l];
         int64_t lo = 1, hi = 0, pr = -1;
-        if (lf.cnt != 0 && G) {
+        if (lf.cnt != 0 && hash_spk) {
+            pr = (int64_t)hash_bucket(lf, x, hash_spk);
+            lo = hi = pr;
+        } else if (lf.cnt != 0 && G) {
             pr = (int64_t)gapped_pred(lf, x, G);
             lo = pr;
             hi = pr + (lf.hi < 0 ? 0 : lf.hi);
@@ -901,28 +1019,32 @@ namespace {
 
 template <int kItems, int kSearch>
 hipError_t launch_probe_items(const TileJob& j, uint32_t* ctr, hipStream_t stream) {
-    dim3 grid(j.ntiles), block(kBlock);
-    switch (j.kind & (kJobFp64 | kJobDup)) {
-        case 0:
-            hipLaunchKernelGGL((probe_join_kernel<LeafF32, true, kItems, kSearch>), grid, block, 0,
-                               stream, j, ctr);
-            break;
-        case kJobDup:
-            if constexpr (kItems <= kItemsDup)
-                hipLaunchKernelGGL((probe_join_kernel<LeafF32, false, kItems, kSearch>), grid, block,
-                                   0, stream, j, ctr);
-            break;
-        case kJobFp64:
-            hipLaunchKernelGGL((probe_join_kernel<LeafF64, true, kItems, kSearch>), grid, block, 0,
-                               stream, j, ctr);
-            break;
-        default:
-            if constexpr (kItems <= kItemsDup)
-                hipLaunchKernelGGL((probe_join_kernel<LeafF64, false, kItems, kSearch>), grid, block,
-                                   0, stream, j, ctr);
-            break;
+    if constexpr (kSearch == kSearchHash && kItems > kItemsHash) {
+        return hipErrorInvalidValue;  // launch_probe caps keys per lane for hash indexes
+    } else {
+        dim3 grid(j.ntiles), block(kBlock);
+        switch (j.kind & (kJobFp64 | kJobDup)) {
+            case 0:
+                hipLaunchKernelGGL((probe_join_kernel<LeafF32, true, kItems, kSearch>), grid,
+                                   block, 0, stream, j, ctr);
+                break;
+            case kJobDup:
+                if constexpr (kItems <= kItemsDup)
+                    hipLaunchKernelGGL((probe_join_kernel<LeafF32, false, kItems, kSearch>),
+                                       grid, block, 0, stream, j, ctr);
+                break;
+            case kJobFp64:
+                hipLaunchKernelGGL((probe_join_kernel<LeafF64, true, kItems, kSearch>), grid,
+                                   block, 0, stream, j, ctr);
+                break;
+            default:
+                if constexpr (kItems <= kItemsDup)
+                    hipLaunchKernelGGL((probe_join_kernel<LeafF64, false, kItems, kSearch>),
+                                       grid, block, 0, stream, j, ctr);
+                break;
+        }
+        return hipGetLastError();
     }
-    return hipGetLastError();
 }
 
 }  // namespace
@@ -943,23 +1065,29 @@ TileJob index_job(const lj_index* idx) {
     j.slots = idx->slots_dev;
     j.nslots = (uint32_t)idx->nslots;
     j.gap = idx->gap;
+    j.buckets = idx->buckets_dev;
+    j.hash_spk = idx->hash_spk;
     return j;
 }
 
 int search_mode(uint32_t kind) {
-    return (kind & kJobGapped) ? kSearchGapped : (kind & kJobExp) ? kSearchExp : kSearchBinary;
+    return (kind & kJobHash)     ? kSearchHash
+           : (kind & kJobGapped) ? kSearchGapped
+           : (kind & kJobExp)    ? kSearchExp
+                                 : kSearchBinary;
 }
 
 template <class Leaf, bool kUnique, int kSearch>
 void launch_binned_search(const lj_index* idx, const uint64_t* keys, uint64_t m, void* res,
                           hipStream_t stream) {
-    constexpr int kItems = kItemsBinned;
+    // A hash probe holds a whole 64-byte bucket per key in registers.
+    constexpr int kItems = kSearch == kSearchHash ? kItemsHash : kItemsBinned;
     const uint32_t nt = (uint32_t)num_tiles(m, (uint64_t)kBlock * kItems);
     const uint32_t per = (nt + kXcds - 1) / kXcds;
     hipLaunchKernelGGL((probe_binned_kernel<Leaf, kUnique, kItems, kSearch>), dim3(per * kXcds),
                        dim3(kBlock), 0, stream, idx->r_dev, (const Leaf*)idx->leaf_dev,
-                       idx->root, idx->slots_dev, (uint32_t)idx->nslots, idx->gap, keys, m, nt,
-                       per, res);
+                       idx->root, idx->slots_dev, (uint32_t)idx->nslots, idx->gap,
+                       idx->buckets_dev, idx->hash_spk, keys, m, nt, per, res);
 }
 
 // Steps of the first pass of the two-pass gapped search, and keys per lane
@@ -994,7 +1122,9 @@ template <class Leaf, bool kUnique>
 void launch_binned_search_any(int search, const lj_index* idx, const uint64_t* keys,
                               uint64_t m, void* res, void* ws, const BinnedWs& L,
                               hipStream_t stream) {
-    if (search == kSearchGapped && kUnique)
+    if (search == kSearchHash)
+        launch_binned_search<Leaf, kUnique, kSearchHash>(idx, keys, m, res, stream);
+    else if (search == kSearchGapped && kUnique)
         launch_binned_gapped<Leaf>(idx, keys, m, res, ws, L, stream);
     else if (search == kSearchGapped)
         launch_binned_search<Leaf, kUnique, kSearchGapped>(idx, keys, m, res, stream);
@@ -1079,8 +1209,13 @@ hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m, lj_p
     if (uses_binned(idx, m, mode))
         return launch_probe_binned(idx, s, m, out, cap, count_dev, ws, stream, ev0, ev1);
     const uint32_t kind = job_kind(idx);
-    if (kpl == 0) kpl = (kind & kJobDup) ? kItemsDup : (kind & kJobGapped) ? kItemsGapped : kItemsUnique;
+    if (kpl == 0)
+        kpl = (kind & kJobHash)     ? kItemsHash
+              : (kind & kJobDup)    ? kItemsDup
+              : (kind & kJobGapped) ? kItemsGapped
+                                    : kItemsUnique;
     if (!probe_kpl_supported(kpl, (kind & kJobDup) != 0)) return hipErrorInvalidValue;
+    if ((kind & kJobHash) && kpl > (uint32_t)kItemsHash) kpl = kItemsHash;
     const uint64_t nt = num_tiles(m, (uint64_t)kBlock * kpl);
     const uint64_t words = (kWsHeaderBytes + nt * 8) / 8;
     hipError_t e = launch_zero_words((uint64_t*)ws, words, stream);
@@ -1106,10 +1241,11 @@ hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m, lj_p
     }
     uint32_t* ctr = &hdr->tile_counter;
     const int search = search_mode(kind);
-#define LJ_ITEMS(K)                                                          \
-    e = search == kSearchGapped ? launch_probe_items<K, kSearchGapped>(j, ctr, stream) \
-        : search == kSearchExp  ? launch_probe_items<K, kSearchExp>(j, ctr, stream)    \
-                                : launch_probe_items<K, kSearchBinary>(j, ctr, stream)
+#define LJ_ITEMS(K)                                                                    \
+    e = search == kSearchHash     ? launch_probe_items<K, kSearchHash>(j, ctr, stream)   \
+        : search == kSearchGapped ? launch_probe_items<K, kSearchGapped>(j, ctr, stream) \
+        : search == kSearchExp    ? launch_probe_items<K, kSearchExp>(j, ctr, stream)    \
+                                  : launch_probe_items<K, kSearchBinary>(j, ctr, stream)
     switch (kpl) {
         case 4: LJ_ITEMS(4); break;
         case 8: LJ_ITEMS(8); break;
@@ -1124,6 +1260,23 @@ hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m, lj_p
 
 hipError_t launch_self_check(const lj_index* idx, uint64_t* viol, hipStream_t stream) {
     hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, stream, viol, (uint64_t)2);
+    if (idx->hash_spk) {
+        unsigned long long* v = (unsigned long long*)viol;
+        const unsigned g = grid_for(idx->n, 256);
+        if (idx->n && leaf_fp32(idx->flags))
+            hipLaunchKernelGGL(self_check_hash_kernel<LeafF32>, dim3(g), dim3(256), 0, stream,
+                               idx->r_dev, idx->n, idx->buckets_dev, idx->nbuckets,
+                               idx->hash_spk, (const LeafF32*)idx->leaf_dev, idx->root, v);
+        else if (idx->n)
+            hipLaunchKernelGGL(self_check_hash_kernel<LeafF64>, dim3(g), dim3(256), 0, stream,
+                               idx->r_dev, idx->n, idx->buckets_dev, idx->nbuckets,
+                               idx->hash_spk, (const LeafF64*)idx->leaf_dev, idx->root, v);
+        hipLaunchKernelGGL(bucket_keys_kernel, dim3(grid_for(idx->nbuckets, 256)), dim3(256), 0,
+                           stream, idx->buckets_dev, idx->nbuckets, v + 1);
+        hipLaunchKernelGGL(finish_gapped_check_kernel, dim3(1), dim3(64), 0, stream, v,
+                           (const unsigned long long*)(v + 1), idx->n);
+        return hipGetLastError();
+    }
     if (idx->gap) {
         unsigned long long* v = (unsigned long long*)viol;
         const unsigned gs = grid_for(idx->nslots, 256);
@@ -1160,11 +1313,11 @@ hipError_t launch_predict_windows(const lj_index* idx, const uint64_t* keys, uin
     if (leaf_fp32(idx->flags))
         hipLaunchKernelGGL(predict_windows_kernel<LeafF32>, dim3(g), dim3(256), 0, stream,
                            keys, m, (const LeafF32*)idx->leaf_dev, idx->root, idx->gap,
-                           idx->nslots, leaf, pred, wlo, whi);
+                           idx->nslots, idx->hash_spk, leaf, pred, wlo, whi);
     else
         hipLaunchKernelGGL(predict_windows_kernel<LeafF64>, dim3(g), dim3(256), 0, stream,
                            keys, m, (const LeafF64*)idx->leaf_dev, idx->root, idx->gap,
-                           idx->nslots, leaf, pred, wlo, whi);
+                           idx->nslots, idx->hash_spk, leaf, pred, wlo, whi);
     return hipGetLastError();
 }
 

@@ -41,6 +41,7 @@ EXPORTED = (
     "lj_server_default_config", "lj_server_create", "lj_server_submit",
     "lj_server_submit_device", "lj_server_wait", "lj_server_get_stats", "lj_server_destroy",
     "lj_build_gapped_rmi", "lj_build_gapped_rmi_host_only", "lj_gapped_slots_host",
+    "lj_build_learned_hash", "lj_build_learned_hash_host_only", "lj_hash_buckets_host",
 )
 GAP_SLOT = 0xFFFFFFFF  # payload of a gap slot in lj_gapped_slots_host
 
@@ -148,6 +149,11 @@ def lib() -> ctypes.CDLL:
         L.lj_build_gapped_rmi.argtypes = [vp, u64, u32, u32, u32, vp, ctypes.POINTER(vp)]
         L.lj_build_gapped_rmi_host_only.argtypes = [vp, u64, u32, u32, u32, ctypes.POINTER(vp)]
         L.lj_gapped_slots_host.argtypes = [vp, vp, vp, u64, ctypes.POINTER(u64)]
+        L.lj_build_learned_hash.argtypes = [vp, u64, u32, u32, u32, vp, ctypes.POINTER(vp)]
+        L.lj_build_learned_hash_host_only.argtypes = [vp, u64, u32, u32, u32,
+                                                      ctypes.POINTER(vp)]
+        L.lj_hash_buckets_host.argtypes = [vp, vp, vp, vp, u64, ctypes.POINTER(u64),
+                                           ctypes.POINTER(u64)]
         L.lj_free_index.argtypes = [vp]
         L.lj_free_index.restype = None
         L.lj_probe_join.argtypes = [vp, vp, u64, vp, u64, ctypes.POINTER(u64), vp]
@@ -299,6 +305,46 @@ def lj_gapped_slots_host(index: Index):
     _check(lib().lj_gapped_slots_host(index.handle, keys.ctypes.data, ridx.ctypes.data, n.value,
                                       ctypes.byref(n)), "lj_gapped_slots_host")
     return keys, ridx
+
+
+def lj_build_learned_hash(r_keys, leaves: int, slots_per_key: int = 4,
+                          flags: int = LJ_LEAF_FP32, stream=None) -> Index:
+    """Build a learned hash index over host array r_keys (sorted uint64)."""
+    R = _host_u64(r_keys)
+    h = ctypes.c_void_p()
+    _check(lib().lj_build_learned_hash(R.ctypes.data if len(R) else None, len(R), leaves,
+                                       slots_per_key, flags, _stream_ptr(stream),
+                                       ctypes.byref(h)), "lj_build_learned_hash")
+    return Index(h.value, False)
+
+
+def lj_build_learned_hash_host_only(r_keys, leaves: int, slots_per_key: int = 4,
+                                    flags: int = LJ_LEAF_FP32) -> Index:
+    R = _host_u64(r_keys)
+    h = ctypes.c_void_p()
+    _check(lib().lj_build_learned_hash_host_only(R.ctypes.data if len(R) else None, len(R),
+                                                 leaves, slots_per_key, flags, ctypes.byref(h)),
+           "lj_build_learned_hash_host_only")
+    return Index(h.value, True)
+
+
+def lj_hash_buckets_host(index: Index):
+    """(keys uint64[nb, 4], ridx uint32[nb, 4], next uint32[nb], nprimary) of
+    a host-only learned hash index; an empty slot has ridx == GAP_SLOT, the
+    end of a chain next == GAP_SLOT."""
+    n = ctypes.c_uint64()
+    npri = ctypes.c_uint64()
+    st = lib().lj_hash_buckets_host(index.handle, None, None, None, 0, ctypes.byref(n),
+                                    ctypes.byref(npri))
+    if st not in (LJ_OK, LJ_ERR_CAPACITY):
+        _check(st, "lj_hash_buckets_host")
+    keys = np.empty((n.value, 4), dtype=np.uint64)
+    ridx = np.empty((n.value, 4), dtype=np.uint32)
+    nxt = np.empty(n.value, dtype=np.uint32)
+    _check(lib().lj_hash_buckets_host(index.handle, keys.ctypes.data, ridx.ctypes.data,
+                                      nxt.ctypes.data, n.value, ctypes.byref(n),
+                                      ctypes.byref(npri)), "lj_hash_buckets_host")
+    return keys, ridx, nxt, npri.value
 
 
 def lj_probe_join(index: Index, s_keys_dev, out_pairs_dev=None, stream=None):

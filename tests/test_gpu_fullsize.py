@@ -1,7 +1,8 @@
 """Full-size parity on the lognormal / Zipf workload (2e8 x 2e8, 2^20 leaves),
 probed the way the benchmark probes it (FP32 leaves, synchronous probe, with
 and without the binned probe, on a plain RMI and on a gapped RMI with 4
-slots per key).
+slots per key); and the sequential-with-holes workload (2e8 x 2e8) on the
+learned hash index and the plain RMI.
 
 The oracle's full sort-merge is too slow on the host at this size, so the
 output is checked by properties that pin it exactly:
@@ -21,17 +22,22 @@ import workloads
 from paper_2111_08824_amd import lj
 
 pytestmark = pytest.mark.gpu
-# (flags, slots per key of a gapped RMI; 0 = plain RMI)
-MODES = [(lj.LJ_LEAF_FP32, 0), (lj.LJ_LEAF_FP32 | lj.LJ_PROBE_BINNED, 0),
-         (lj.LJ_LEAF_FP32, 4), (lj.LJ_LEAF_FP32 | lj.LJ_PROBE_BINNED, 4)]
+BIN = lj.LJ_PROBE_BINNED
+# (flags, index kind, slots per key)
+MODES = [(lj.LJ_LEAF_FP32, "rmi", 0), (lj.LJ_LEAF_FP32 | BIN, "rmi", 0),
+         (lj.LJ_LEAF_FP32, "gapped", 4), (lj.LJ_LEAF_FP32 | BIN, "gapped", 4)]
+HASH_MODES = [(lj.LJ_LEAF_FP32, "hash", 4), (lj.LJ_LEAF_FP32 | BIN, "hash", 4),
+              (lj.LJ_LEAF_FP32 | BIN, "rmi", 0)]
 
 
 def build(w, mode):
-    flags, spk = mode
-    print(f"[fullsize] building index (fp32 leaves, {w.leaves}, flags {flags}, "
+    flags, kind, spk = mode
+    print(f"[fullsize] building {kind} index (fp32 leaves, {w.leaves}, flags {flags}, "
           f"slots/key {spk})", flush=True)
-    if spk:
+    if kind == "gapped":
         return lj.lj_build_gapped_rmi(w.R, w.leaves, spk, flags)
+    if kind == "hash":
+        return lj.lj_build_learned_hash(w.R, w.leaves, spk, flags)
     return lj.lj_build_rmi(w.R, w.leaves, flags)
 
 
@@ -52,10 +58,12 @@ def c3():
     return w, want
 
 
-@pytest.mark.parametrize("mode", MODES)
-def test_lognormal_zipf_200m_full_size(c2, mode):
+def check_unique_full_size(w, mode, seed):
+    """R without duplicates and an exactly known hit count: every pair
+    matches, pairs strictly increase in s, |output| == the generator's hit
+    count, and 200,000 sampled outer keys agree with the oracle's
+    equal_range."""
     import torch
-    w = c2
     ix = build(w, mode)
     assert lj.lj_self_check(ix) == 0
     s = lj.to_device_keys(w.S)
@@ -70,7 +78,7 @@ def test_lognormal_zipf_200m_full_size(c2, mode):
     ri = P[:, 1].astype(np.int64)
     assert np.all(np.diff(si) > 0)
     assert np.array_equal(w.S[si], w.R[ri])
-    rng = np.random.default_rng(1)
+    rng = np.random.default_rng(seed)
     sample = rng.choice(len(w.S), 200_000, replace=False)
     first, count = oracle.equal_range(w.R, w.S[sample])
     pos = np.searchsorted(si, sample)
@@ -78,6 +86,22 @@ def test_lognormal_zipf_200m_full_size(c2, mode):
     emitted = si[pos_c] == sample
     assert np.array_equal(emitted, count == 1)
     assert np.array_equal(ri[pos_c][emitted], first[emitted].astype(np.int64))
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_lognormal_zipf_200m_full_size(c2, mode):
+    check_unique_full_size(c2, mode, 1)
+
+
+@pytest.fixture(scope="module")
+def c6():
+    print("[fullsize] generating seq-holes-200M", flush=True)
+    return workloads.c6_seq_holes()
+
+
+@pytest.mark.parametrize("mode", HASH_MODES)
+def test_seq_holes_200m_full_size(c6, mode):
+    check_unique_full_size(c6, mode, 3)
 
 
 @pytest.mark.parametrize("mode", MODES)

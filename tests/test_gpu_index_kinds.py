@@ -1,10 +1,11 @@
-"""GPU parity of the gapped RMI (Section III-A, "Gapped RMI"): probes of a
-gapped index through the C ABI, in every probe form (fused direct probe,
-binned probe, batched plan, serving loop), compared element by element with
-the oracle's sort-merge join on the same seeded inputs.  The join output is
-integer index work, so the bar is exact equality in (s_idx, r_idx) order;
-the device self-check must also find every key slot of R intact and inside
-its slot window."""
+"""GPU parity of the two index kinds built over the RMI: the gapped RMI
+(Section III-A, "Gapped RMI") and the learned hash index (Section III-C,
+"Learned-based Hash INLJ").  Probes of each kind through the C ABI, in every
+probe form (fused direct probe, binned probe, batched plan, serving loop),
+are compared element by element with the oracle's sort-merge join on the
+same seeded inputs.  The join output is integer index work, so the bar is
+exact equality in (s_idx, r_idx) order; the device self-check must also find
+every key of R intact where the index says it is."""
 import numpy as np
 import pytest
 
@@ -17,14 +18,18 @@ pytestmark = pytest.mark.gpu
 U64MAX = 2**64 - 1
 BIN = lj.LJ_PROBE_BINNED
 FLAGS = [lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP64, lj.LJ_LEAF_FP32 | BIN, lj.LJ_LEAF_FP64 | BIN]
+KINDS = ["gapped", "hash"]
+BUILD = {"gapped": lj.lj_build_gapped_rmi, "hash": lj.lj_build_learned_hash}
+BUILD_HOST = {"gapped": lj.lj_build_gapped_rmi_host_only,
+              "hash": lj.lj_build_learned_hash_host_only}
 
 
-def assert_gapped_parity(R, S, leaves, flags, spk=4, label=""):
-    print(f"[gapped] {label} n={len(R)} m={len(S)} leaves={leaves} flags={flags} "
+def assert_parity(kind, R, S, leaves, flags, spk=4, label=""):
+    print(f"[{kind}] {label} n={len(R)} m={len(S)} leaves={leaves} flags={flags} "
           f"slots/key={spk}", flush=True)
     R = np.asarray(R, dtype=np.uint64)
     S = np.asarray(S, dtype=np.uint64)
-    ix = lj.lj_build_gapped_rmi(R, leaves, spk, flags)
+    ix = BUILD[kind](R, leaves, spk, flags)
     assert ix.stats.slots_per_key == spk
     assert lj.lj_self_check(ix) == 0
     got = lj.probe(ix, lj.to_device_keys(S)).cpu().numpy().view(np.uint32).reshape(-1, 2)
@@ -34,68 +39,76 @@ def assert_gapped_parity(R, S, leaves, flags, spk=4, label=""):
     return ix, got
 
 
+@pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("flags", FLAGS)
-def test_workloads(flags):
+def test_workloads(kind, flags):
     w = workloads.c1_uniform(scale=0.5)
-    assert_gapped_parity(w.R, w.S, w.leaves, flags, 4, w.name)
+    assert_parity(kind, w.R, w.S, w.leaves, flags, 4, w.name)
     w = workloads.c2_lognormal_zipf(scale=0.01)
-    assert_gapped_parity(w.R, w.S, w.leaves, flags, 4, w.name)
+    assert_parity(kind, w.R, w.S, w.leaves, flags, 4, w.name)
     w = workloads.c3_dup_runs(scale=0.01)
-    assert_gapped_parity(w.R, w.S, w.leaves, flags, 4, w.name)
+    assert_parity(kind, w.R, w.S, w.leaves, flags, 4, w.name)
+    w = workloads.c6_seq_holes(scale=0.01)
+    assert_parity(kind, w.R, w.S, w.leaves, flags, 4, w.name)
 
 
+@pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("spk", [1, 2, 16])
-def test_slots_per_key(spk):
+def test_slots_per_key(kind, spk):
     w = workloads.c2_lognormal_zipf(scale=0.005)
     for flags in (lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP32 | BIN):
-        assert_gapped_parity(w.R, w.S, w.leaves, flags, spk, w.name)
+        assert_parity(kind, w.R, w.S, w.leaves, flags, spk, w.name)
     w = workloads.c3_dup_runs(scale=0.003)
-    assert_gapped_parity(w.R, w.S, w.leaves, lj.LJ_LEAF_FP32, spk, w.name)
+    assert_parity(kind, w.R, w.S, w.leaves, lj.LJ_LEAF_FP32, spk, w.name)
 
 
+@pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("m", [1, 63, 1025, 4096 + 7, 77_777])
 @pytest.mark.parametrize("binned", [0, BIN])
-def test_ragged_tile_tails(m, binned):
+def test_ragged_tile_tails(kind, m, binned):
     R = workloads.gen.uniform_unique(50_000, 20, 3)
     S = workloads.gen.probe_mix(R, m, 0.6, 4, miss_hi=2**20)
-    assert_gapped_parity(R, S, 256, lj.LJ_LEAF_FP32 | binned, 4, f"tail m={m}")
+    assert_parity(kind, R, S, 256, lj.LJ_LEAF_FP32 | binned, 4, f"tail m={m}")
 
 
+@pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("leaves", [1, 1000, 200_003])
-def test_leaf_counts(leaves):
+def test_leaf_counts(kind, leaves):
     R = workloads.gen.lognormal_unique(50_000, 2.0, 5)
     S = workloads.gen.probe_mix(R, 60_000, 0.5, 6, miss_hi=2**63)
-    assert_gapped_parity(R, S, leaves, lj.LJ_LEAF_FP32, 4, f"leaves={leaves}")
+    assert_parity(kind, R, S, leaves, lj.LJ_LEAF_FP32, 4, f"leaves={leaves}")
 
 
-def test_extreme_keys_and_degenerate_relations():
+@pytest.mark.parametrize("kind", KINDS)
+def test_extreme_keys_and_degenerate_relations(kind):
     R = np.array([0, 0, 1, 2**63, U64MAX - 1, U64MAX, U64MAX], dtype=np.uint64)
     S = np.array([U64MAX, 0, 7, 2**63, U64MAX - 2, 1, U64MAX], dtype=np.uint64)
     for flags in FLAGS:
-        assert_gapped_parity(R, S, 3, flags, 4, "extreme keys")
+        assert_parity(kind, R, S, 3, flags, 4, "extreme keys")
     # UINT64_MAX absent from R: trailing gaps hold it but are no match.
     miss = np.array([U64MAX, U64MAX - 1, U64MAX, 5, 3], dtype=np.uint64)
     for R in ([0, 5, U64MAX - 1], [0, 5, 5, U64MAX - 1], [5], [7] * 1000):
         for flags in (lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP32 | BIN):
-            assert_gapped_parity(R, miss, 2, flags, 4, f"n={len(R)}")
+            assert_parity(kind, R, miss, 2, flags, 4, f"n={len(R)}")
     heavy = np.concatenate([np.arange(0, 100, dtype=np.uint64),
                             np.full(5000, 1000, dtype=np.uint64),
                             np.arange(2000, 2100, dtype=np.uint64)])
     S = np.array([1000, 5, 1000, 7000, 2050, 1000], dtype=np.uint64)
-    _, got = assert_gapped_parity(heavy, S, 8, lj.LJ_LEAF_FP32, 4, "heavy duplicates")
+    _, got = assert_parity(kind, heavy, S, 8, lj.LJ_LEAF_FP32, 4, "heavy duplicates")
     assert len(got) == 3 * 5000 + 2
 
 
+@pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("binned", [0, BIN])
-def test_empty_inputs_and_capacity(binned):
+def test_empty_inputs_and_capacity(kind, binned):
     import torch
-    ix0 = lj.lj_build_gapped_rmi(np.empty(0, dtype=np.uint64), 4, 4, lj.LJ_LEAF_FP32 | binned)
+    ix0 = BUILD[kind](np.empty(0, dtype=np.uint64), 4, 4, lj.LJ_LEAF_FP32 | binned)
     assert lj.lj_self_check(ix0) == 0
     s = lj.to_device_keys(np.array([0, 1, U64MAX], dtype=np.uint64))
     assert lj.lj_probe_join(ix0, s) == (lj.LJ_OK, 0)
     w = workloads.c3_dup_runs(scale=0.001)
     want = oracle.sort_merge_join(w.R, w.S)
-    ix = lj.lj_build_gapped_rmi(w.R, w.leaves, 4, lj.LJ_LEAF_FP32 | binned)
+    ix = BUILD[kind](w.R, w.leaves, 4, lj.LJ_LEAF_FP32 | binned)
     s = lj.to_device_keys(w.S)
     assert lj.lj_probe_join(ix, lj.to_device_keys(w.S[:0])) == (lj.LJ_OK, 0)
     assert lj.lj_probe_join(ix, s, None) == (lj.LJ_OK, len(want))
@@ -106,12 +119,13 @@ def test_empty_inputs_and_capacity(binned):
     assert np.array_equal(out.cpu().numpy().view(np.uint32), want[:cap])
 
 
-def test_device_windows_equal_host_windows():
+@pytest.mark.parametrize("kind", KINDS)
+def test_device_windows_equal_host_windows(kind):
     import torch
     w = workloads.c2_lognormal_zipf(scale=0.002)
     for flags in (lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP64):
-        host = lj.lj_build_gapped_rmi_host_only(w.R, w.leaves, 4, flags)
-        ix = lj.lj_build_gapped_rmi(w.R, w.leaves, 4, flags)
+        host = BUILD_HOST[kind](w.R, w.leaves, 4, flags)
+        ix = BUILD[kind](w.R, w.leaves, 4, flags)
         keys = np.concatenate([w.R, w.S])
         want = lj.lj_predict_windows_host(host, keys)
         assert np.array_equal(lj.lj_predict_windows_host(ix, keys)[1], want[1])
@@ -126,14 +140,15 @@ def test_device_windows_equal_host_windows():
 
 
 @pytest.mark.parametrize("binned_min_keys", [0, 1])
-def test_batched_plan_mixes_gapped_and_plain_indexes(binned_min_keys):
+def test_batched_plan_mixes_index_kinds(binned_min_keys):
     import torch
     ws = workloads.multi_index_batches(k=6, seed=11, n_lo=1e3, n_hi=2e5, m_lo=1, m_hi=2e5)
     ws.append(workloads.c3_dup_runs(seed=11, scale=0.002))
     items = []
     for i, w in enumerate(ws):
         flags = lj.LJ_LEAF_FP64 if i % 3 == 1 else lj.LJ_LEAF_FP32
-        ix = (lj.lj_build_gapped_rmi(w.R, w.leaves, 1 + i % 5, flags) if i % 2 == 0
+        ix = (lj.lj_build_gapped_rmi(w.R, w.leaves, 1 + i % 5, flags) if i % 3 == 0
+              else lj.lj_build_learned_hash(w.R, w.leaves, 1 + i % 7, flags) if i % 3 == 1
               else lj.lj_build_rmi(w.R, w.leaves, flags))
         cap = max(1, len(w.S) * int(ix.stats.max_mult))
         out = torch.full((cap, 2), -1, dtype=torch.int32, device="cuda")
@@ -143,7 +158,7 @@ def test_batched_plan_mixes_gapped_and_plain_indexes(binned_min_keys):
     t.binned_min_keys = binned_min_keys
     plan = lj.BatchPlan([(ix, s, out, cnt) for _, ix, s, out, cnt in items], t)
     for rep in range(2):
-        print(f"[gapped] plan replay {rep} binned_min_keys={binned_min_keys}", flush=True)
+        print(f"[kinds] plan replay {rep} binned_min_keys={binned_min_keys}", flush=True)
         for *_, out, cnt in items:
             out.fill_(-1)
             cnt.fill_(-7)
@@ -156,16 +171,18 @@ def test_batched_plan_mixes_gapped_and_plain_indexes(binned_min_keys):
             assert np.array_equal(out[:n].cpu().numpy().view(np.uint32), want)
 
 
-def test_server_with_gapped_index():
-    ws = [workloads.c2_lognormal_zipf(seed=21, scale=0.002), workloads.c1_uniform(seed=22)]
-    ixs = [lj.lj_build_gapped_rmi(ws[0].R, ws[0].leaves, 4), lj.lj_build_rmi(ws[1].R, ws[1].leaves)]
+def test_server_with_gapped_and_hash_indexes():
+    ws = [workloads.c2_lognormal_zipf(seed=21, scale=0.002), workloads.c1_uniform(seed=22),
+          workloads.c6_seq_holes(seed=23, scale=0.002)]
+    ixs = [lj.lj_build_gapped_rmi(ws[0].R, ws[0].leaves, 4), lj.lj_build_rmi(ws[1].R, ws[1].leaves),
+           lj.lj_build_learned_hash(ws[2].R, ws[2].leaves, 4)]
     cfg = lj.lj_server_default_config(256 << 20)
     srv = lj.Server(ixs, cfg)
     try:
         tickets = []
         rng = np.random.default_rng(5)
         for k in range(12):
-            i = k % 2
+            i = k % 3
             a = int(rng.integers(0, len(ws[i].S) - 1000))
             S = ws[i].S[a:a + 1 + int(rng.integers(0, 20_000))]
             want = oracle.sort_merge_join(ws[i].R, S)

@@ -91,3 +91,12 @@ def test_workload_defaults():
     assert workloads.default_leaves(1_000_000) == 4096
     assert workloads.default_leaves(200_000_000) == 2**20
     assert workloads.default_leaves(10) == 1
+
+
+def test_seq_holes_workload_exact_hits():
+    w = workloads.c6_seq_holes(scale=0.001)
+    assert np.all(w.R[1:] > w.R[:-1])
+    hits = np.isin(w.S, w.R)
+    assert int(hits.sum()) == w.expected_count == int(round(len(w.S) * 0.9))
+    # Misses are holes or above the largest key.
+    assert not np.any(np.isin(w.S[~hits], w.R))

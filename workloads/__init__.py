@@ -15,6 +15,6 @@ from .gen import (  # noqa: F401
     probe_mix, permute, shuffle,
 )
 from .configs import (  # noqa: F401
-    Workload, c1_uniform, c2_lognormal_zipf, c3_dup_runs, multi_index_batches,
+    Workload, c1_uniform, c2_lognormal_zipf, c3_dup_runs, c6_seq_holes, multi_index_batches,
     default_leaves, resident_indexes,
 )

@@ -11,6 +11,9 @@ Full sizes:
                      times, 2^19 leaves; S = 1e8 keys, 70% hits uniform over
                      the distinct values, 30% misses (holes and values above
                      the largest key).
+  c6_seq_holes       R = 2e8 sequential IDs with 10% random holes (seq_h),
+                     2^20 leaves; S = 2e8 keys, 90% hits uniform over R,
+                     10% misses (holes and values above the largest key).
   multi_index_batches  many independent inner relations of log-uniform size
                      and mixed shape, each probed by one batch of
                      log-uniform size with 50% hits.
@@ -79,6 +82,16 @@ def c3_dup_runs(seed: int = 42, scale: float = 1.0) -> Workload:
     return Workload("dup-runs-100M" if scale == 1.0 else f"dup-runs-{rows}", R, S,
                     _scaled_leaves(2**19, scale), None,
                     {"n": rows, "m": m, "hit_frac": 0.7, "dist": "seq_h x U{1..16}"})
+
+
+def c6_seq_holes(seed: int = 42, scale: float = 1.0) -> Workload:
+    n, m = _scaled(200_000_000, scale), _scaled(200_000_000, scale)
+    R = gen.seq_holes(n, seed)
+    top = int(R[-1]) if n else 0
+    S = gen.probe_mix(R, m, 0.9, seed + 1, miss_lo=0, miss_hi=top + top // 8 + 2)
+    return Workload("seq-holes-200M" if scale == 1.0 else f"seq-holes-{n}", R, S,
+                    _scaled_leaves(2**20, scale), int(round(m * 0.9)),
+                    {"n": n, "m": m, "hit_frac": 0.9, "dist": "seq_h (10% holes)"})
 
 
 def multi_index_batches(k: int = 64, seed: int = 42, n_lo: float = 1e4,

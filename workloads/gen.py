@@ -252,7 +252,11 @@ def probe_mix(R: np.ndarray, m: int, hit_frac: float, seed: int, *,
         cand = draw_range(mkey, start, want, miss_lo, miss_hi - miss_lo)
         start += want
         if nd:
-            j = np.searchsorted(distinct, cand)
+            # Membership by binary search, queries in sorted order (random
+            # queries into a large array miss the cache at every step).
+            order = np.argsort(cand, kind="stable")
+            j = np.empty(len(cand), dtype=np.int64)
+            j[order] = np.searchsorted(distinct, cand[order])
             j[j >= nd] = nd - 1
             cand = cand[distinct[j] != cand]
         take = cand[: n_miss - got]
