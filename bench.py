@@ -455,7 +455,9 @@ def main():
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": load_traffic(w.name, binned, args.index),
             "algorithmic_bytes_per_launch": alg,
-            "kernel": "probe_binned_kernel" if binned else "probe_join_kernel",
+            "kernel": (("probe_binned_gapped_kernel+gapped_queue_kernel"
+                        if gapped and st.max_mult <= 1 else "probe_binned_kernel")
+                       if binned else "probe_join_kernel"),
             "kernel_ms": round(kern_ms, 4)}
 
     cpu = cpu_baseline(w, min(args.cpu_sample, m)) if args.cpu_sample else None

@@ -362,8 +362,10 @@ int lj_server_submit(lj_server* server, uint32_t index_id, const uint64_t* s_key
  * the server's GPU (for producers and consumers on the GPU): no copies are
  * made; the probe reads s_keys_dev and writes up to out_capacity pairs to
  * out_pairs_dev directly, and only its workspace and count word come from
- * the arena.  Both buffers must stay valid and untouched until the request
- * completes.  Same tickets, results and errors as lj_server_submit.
+ * the arena.  The server's streams do not wait for the caller's: the work
+ * that writes the keys (or last uses the pair buffer) must be complete when
+ * this is called.  Both buffers must stay valid and untouched until the
+ * request completes.  Same tickets, results and errors as lj_server_submit.
  */
 int lj_server_submit_device(lj_server* server, uint32_t index_id,
                             const uint64_t* s_keys_dev, uint64_t m,

@@ -507,8 +507,10 @@ class Server:
 
     def submit_device(self, index_id: int, s_keys_dev, out_pairs_dev) -> int:
         """Device-resident request: s_keys_dev an int64 CUDA tensor of keys,
-        out_pairs_dev an (cap, 2) int32 CUDA tensor or None; both must stay
-        alive and untouched until wait() returns for the ticket."""
+        out_pairs_dev an (cap, 2) int32 CUDA tensor or None; the work that
+        writes them must be complete (the server's streams do not wait for
+        torch's), and both must stay alive and untouched until wait()
+        returns for the ticket."""
         m = s_keys_dev.numel()
         cap = 0 if out_pairs_dev is None else out_pairs_dev.shape[0]
         t = ctypes.c_uint64()

@@ -139,6 +139,9 @@ def test_device_requests_mixed_with_host_requests(binned_min_keys):
         if q % 2:
             s_dev = lj.to_device_keys(S)
             o_dev = torch.full((max(cap, 1), 2), -1, dtype=torch.int32, device="cuda")
+            # The server's streams do not wait for torch's: the key copy and
+            # the fill must be done before the request is submitted.
+            torch.cuda.synchronize()
             dev_bufs.append((s_dev, o_dev))
             tickets.append(srv.submit_device(i, s_dev, o_dev if cap else None))
         else:
