@@ -194,3 +194,16 @@ def test_server_with_gapped_and_hash_indexes():
             assert np.array_equal(out[: len(want)], want)
     finally:
         srv.close()
+
+
+@pytest.mark.parametrize("spk", [1, 2])
+def test_gapped_search_queue_overflow(spk):
+    """One leaf over lognormal keys: most keys land far from their predicted
+    slot, so after the first pass of the two-pass binned search far more
+    than a quarter of the keys are still open and most waves find the queue
+    full and finish their keys in the first pass; the result must not
+    change."""
+    R = workloads.gen.lognormal_unique(200_000, 2.0, 17)
+    S = workloads.gen.probe_mix(R, 300_000, 0.8, 18, miss_hi=2**63)
+    ix, got = assert_parity("gapped", R, S, 1, lj.LJ_LEAF_FP32 | BIN, spk, "queue overflow")
+    assert ix.stats.mean_window > 100  # the windows really are wide
