@@ -169,17 +169,20 @@ int build_device(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves, uint3
     const uint64_t bbytes = idx->bucket_lo.size() * sizeof(uint16_t);
     const uint64_t sbytes = idx->slots.size() * sizeof(lj::GSlot);
     const uint64_t hbytes = idx->buckets.size() * sizeof(lj::HBucket);
+    const uint64_t nrs = (n + lj::kLineKeys - 1) / lj::kLineKeys;
+    const uint64_t rsbytes = nrs * sizeof(uint64_t);
     if (hipMalloc((void**)&idx->r_dev, rbytes) != hipSuccess ||
         hipMalloc(&idx->leaf_dev, lbytes) != hipSuccess ||
         (fbytes && hipMalloc((void**)&idx->fences_dev, fbytes) != hipSuccess) ||
         (bbytes && hipMalloc((void**)&idx->bucket_lo_dev, bbytes) != hipSuccess) ||
         (sbytes && hipMalloc((void**)&idx->slots_dev, sbytes) != hipSuccess) ||
-        (hbytes && hipMalloc((void**)&idx->buckets_dev, hbytes) != hipSuccess)) {
+        (hbytes && hipMalloc((void**)&idx->buckets_dev, hbytes) != hipSuccess) ||
+        (rsbytes && hipMalloc((void**)&idx->rs_dev, rsbytes) != hipSuccess)) {
         (void)hipGetLastError();
         lj_free_index(idx);
         return LJ_ERR_OOM;
     }
-    idx->device_bytes = rbytes + lbytes + fbytes + bbytes + sbytes + hbytes;
+    idx->device_bytes = rbytes + lbytes + fbytes + bbytes + sbytes + hbytes + rsbytes;
     hipError_t e = hipSuccess;
     if (n) e = hipMemcpyAsync(idx->r_dev, r_keys_host, n * sizeof(uint64_t),
                               hipMemcpyHostToDevice, stream);
@@ -197,6 +200,8 @@ int build_device(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves, uint3
     if (e == hipSuccess && hbytes)
         e = hipMemcpyAsync(idx->buckets_dev, idx->buckets.data(), hbytes, hipMemcpyHostToDevice,
                            stream);
+    if (e == hipSuccess && rsbytes)
+        e = lj::launch_line_samples(idx->r_dev, n, idx->rs_dev, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
         lj_free_index(idx);
@@ -220,6 +225,7 @@ void lj_free_index(lj_index* idx) {
     if (idx->bucket_lo_dev) (void)hipFree(idx->bucket_lo_dev);
     if (idx->slots_dev) (void)hipFree(idx->slots_dev);
     if (idx->buckets_dev) (void)hipFree(idx->buckets_dev);
+    if (idx->rs_dev) (void)hipFree(idx->rs_dev);
     delete idx;
 }
 

@@ -83,6 +83,10 @@ struct lj_index {
 
     // device copies
     uint64_t* r_dev = nullptr;
+    // Line samples of R: rs[i] = R[kLineKeys * i], one key per 128-byte line
+    // (the first stage of the binary search reads these, the second the one
+    // line of R that holds the lower bound).
+    uint64_t* rs_dev = nullptr;
     void* leaf_dev = nullptr;
     uint64_t* fences_dev = nullptr;
     uint16_t* bucket_lo_dev = nullptr;
@@ -134,6 +138,7 @@ __host__ __device__ inline uint64_t gapped_pred(const Leaf& lf, uint64_t x, uint
 // kItemsGapped on a gapped index without duplicates, whose search state
 // needs more registers).
 constexpr int kBlock = 256;
+constexpr uint32_t kLineKeys = 16;  // keys of R per 128-byte cache line (line samples)
 constexpr int kItemsUnique = 24;
 constexpr int kItemsDup = 16;
 constexpr int kItemsGapped = 8;
@@ -248,6 +253,7 @@ inline uint64_t ws_bytes(const lj_index* idx, uint64_t m, int mode = -1) {
 // against one index.
 struct TileJob {
     const uint64_t* r;
+    const uint64_t* rs;    // line samples of R
     const void* leaves;
     RootModel root;
     const uint64_t* s;
@@ -302,6 +308,8 @@ hipError_t launch_unpermute_count(const uint32_t* dest, const void* in, void* ou
                                   bool wide, void* ws, const BinnedWs& layout,
                                   hipStream_t stream);
 hipError_t launch_set_u64(uint64_t* p, uint64_t v, hipStream_t stream);
+// rs[i] = r[kLineKeys * i] for i < ceil(n / kLineKeys).
+hipError_t launch_line_samples(const uint64_t* r, uint64_t n, uint64_t* rs, hipStream_t stream);
 hipError_t launch_zero_words(uint64_t* p, uint64_t nwords, hipStream_t stream);
 // violations_dev: two words (the count, then scratch for a gapped index).
 hipError_t launch_self_check(const lj_index* idx, uint64_t* violations_dev,

@@ -104,7 +104,8 @@ __device__ void finish_tile(const TileJob& j) {
 // in R (inside its window) and c[k] the number of R keys equal to it (0 for
 // a miss or a key past the end of s).
 template <class Leaf, bool kUnique, int kItems, bool kExp>
-__device__ __forceinline__ void search_keys(const uint64_t* __restrict__ R, const Leaf* leaves,
+__device__ __forceinline__ void search_keys(const uint64_t* __restrict__ R,
+                                            const uint64_t* __restrict__ RS, const Leaf* leaves,
                                             const RootModel& root, const uint64_t* s,
                                             const uint64_t m, const uint64_t tbase,
                                             const uint32_t kpl, uint32_t (&first)[kItems],
@@ -213,31 +214,68 @@ __device__ __forceinline__ void search_keys(const uint64_t* __restrict__ R, cons
 #pragma unroll
         for (int k = 0; k < kItems; ++k) first[k] = (uint32_t)hi[k];
     } else {
-        // 3: lockstep lower_bound over the windows.  Finished keys re-read R[0]
-        // (a cached line) so that the loop body has no branches and the loads of
-        // all keys of the lane issue back to back.  When the loop ends, first[k]
-        // is the window end or the position of the last element read with
-        // R[mid] >= x[k], so bit k of eqmask tells whether x[k] was found.
-        for (;;) {
-            uint32_t anylen = 0;
+        // 3: lockstep lower_bound over the windows, in two stages (below).
+        // In each, finished keys re-read A[0] (a cached line) so that the
+        // loop body has no branches and the loads of all keys of the lane
+        // issue back to back.  When a stage ends, first[k] is its range's
+        // end or the position of the last element read with A[mid] >= x[k],
+        // so bit k of eqmask tells whether that element equals x[k].
+        auto bisect = [&](const uint64_t* __restrict__ A) {
+            for (;;) {
+                uint32_t anylen = 0;
 #pragma unroll
-            for (int k = 0; k < kItems; ++k) anylen |= len[k];
-            if (!anylen) break;
-            uint64_t v[kItems];
+                for (int k = 0; k < kItems; ++k) anylen |= len[k];
+                if (!anylen) break;
+                uint64_t v[kItems];
 #pragma unroll
-            for (int k = 0; k < kItems; ++k) v[k] = R[len[k] ? first[k] + (len[k] >> 1) : 0];
+                for (int k = 0; k < kItems; ++k) v[k] = A[len[k] ? first[k] + (len[k] >> 1) : 0];
 #pragma unroll
-            for (int k = 0; k < kItems; ++k) {
-                const uint32_t half = len[k] >> 1;
-                const uint32_t act = len[k] != 0 ? 1u : 0u;
-                const uint32_t lt = v[k] < x[k] ? act : 0u;   // act && lt
-                const uint32_t ge = act ^ lt;                   // act && !lt
-                const uint32_t eq = v[k] == x[k] ? 1u : 0u;
-                first[k] += lt * (half + 1);
-                eqmask = (eqmask & ~(ge << k)) | ((eq & ge) << k);
-                len[k] = lt ? len[k] - half - 1 : half;
+                for (int k = 0; k < kItems; ++k) {
+                    const uint32_t half = len[k] >> 1;
+                    const uint32_t act = len[k] != 0 ? 1u : 0u;
+                    const uint32_t lt = v[k] < x[k] ? act : 0u;   // act && lt
+                    const uint32_t ge = act ^ lt;                   // act && !lt
+                    const uint32_t eq = v[k] == x[k] ? 1u : 0u;
+                    first[k] += lt * (half + 1);
+                    eqmask = (eqmask & ~(ge << k)) | ((eq & ge) << k);
+                    len[k] = lt ? len[k] - half - 1 : half;
+                }
             }
+        };
+        // Two stages.  The window [a, e) holds the line samples c0..c1
+        // (positions kLineKeys*c in [a, e)); their lower bound i (c0..c1
+        // + 1) leaves one candidate range: positions after sample i - 1
+        // (which is < x) up to sample i (which is >= x), clipped to the
+        // window, at most kLineKeys - 1 positions of one line of R.  A
+        // found sample i at the range's end sets the found bit the way a
+        // read of R there would.  The samples are a sixteenth of R (one
+        // per 128-byte line), so the first stage's reads stay in a
+        // smaller, better-cached array and one line of R is read per
+        // key.
+        uint32_t a[kItems], e[kItems];
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            a[k] = first[k];
+            e[k] = first[k] + len[k];
+            const uint32_t c0 = (a[k] + kLineKeys - 1) / kLineKeys;
+            const uint32_t c1 = len[k] ? (e[k] - 1) / kLineKeys : 0u;
+            const bool some = len[k] != 0 && c1 >= c0;
+            first[k] = c0;
+            len[k] = some ? c1 - c0 + 1 : 0u;
         }
+        bisect(RS);
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const uint32_t i = first[k];
+            const uint32_t c0 = (a[k] + kLineKeys - 1) / kLineKeys;
+            const bool past = e[k] <= i * kLineKeys;  // no sample >= x in the window
+            const uint32_t lo = i == c0 ? a[k] : i * kLineKeys - (kLineKeys - 1);
+            const uint32_t hi = past ? e[k] : i * kLineKeys;
+            eqmask &= ~((past ? 1u : 0u) << k);
+            first[k] = lo;
+            len[k] = e[k] > a[k] ? hi - lo : 0u;
+        }
+        bisect(R);
     }
 
     // 4: run lengths.
@@ -656,8 +694,8 @@ __device__ __forceinline__ void probe_tile(const TileJob& j, const uint32_t tile
                                                   (uint64_t)tile * kBlock * kpl, kpl, first, c);
     else
         search_keys<Leaf, kUnique, kItems, kSearch == kSearchExp>(
-            j.r, (const Leaf*)j.leaves, j.root, j.s, j.m, (uint64_t)tile * kBlock * kpl, kpl,
-            first, c);
+            j.r, j.rs, (const Leaf*)j.leaves, j.root, j.s, j.m, (uint64_t)tile * kBlock * kpl,
+            kpl, first, c);
     emit_tile<kUnique, kItems, kWithOffsets>(j, tile, kpl, sh, first, c);
 }
 
@@ -679,8 +717,8 @@ __global__ __launch_bounds__(kBlock) void probe_join_kernel(TileJob j, uint32_t*
 // key as well.
 template <class Leaf, bool kUnique, int kItems, int kSearch>
 __global__ __launch_bounds__(kBlock) void probe_binned_kernel(
-    const uint64_t* __restrict__ R, const Leaf* leaves, RootModel root,
-    const GSlot* __restrict__ slots, uint32_t nslots, uint32_t G,
+    const uint64_t* __restrict__ R, const uint64_t* __restrict__ RS, const Leaf* leaves,
+    RootModel root, const GSlot* __restrict__ slots, uint32_t nslots, uint32_t G,
     const HBucket* __restrict__ buckets, uint32_t hash_spk, const uint64_t* keys,
     uint64_t m, uint32_t ntiles, uint32_t tiles_per_xcd, void* res) {
     const uint32_t slot = blockIdx.x / kXcds;
@@ -695,7 +733,7 @@ __global__ __launch_bounds__(kBlock) void probe_binned_kernel(
         search_keys_gapped<Leaf, kUnique, kItems>(slots, nslots, G, leaves, root, keys, m, tbase,
                                                   kItems, first, c);
     else
-        search_keys<Leaf, kUnique, kItems, kSearch == kSearchExp>(R, leaves, root, keys, m,
+        search_keys<Leaf, kUnique, kItems, kSearch == kSearchExp>(R, RS, leaves, root, keys, m,
                                                                   tbase, kItems, first, c);
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
@@ -870,6 +908,13 @@ __global__ void zero_words(uint64_t* w, uint64_t nwords) {
         w[i] = 0;
 }
 
+__global__ void line_samples_kernel(const uint64_t* __restrict__ r, uint64_t ns,
+                                    uint64_t* __restrict__ rs) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        rs[i] = r[i * kLineKeys];
+}
+
 __global__ void set_u64_kernel(uint64_t* p, uint64_t v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
@@ -1005,6 +1050,15 @@ unsigned grid_for(uint64_t work, unsigned block) {
 
 }  // namespace
 
+hipError_t launch_line_samples(const uint64_t* r, uint64_t n, uint64_t* rs,
+                               hipStream_t stream) {
+    const uint64_t ns = (n + kLineKeys - 1) / kLineKeys;
+    if (ns == 0) return hipSuccess;
+    hipLaunchKernelGGL(line_samples_kernel, dim3(grid_for(ns, 256)), dim3(256), 0, stream, r, ns,
+                       rs);
+    return hipGetLastError();
+}
+
 hipError_t launch_set_u64(uint64_t* p, uint64_t v, hipStream_t stream) {
     hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(64), 0, stream, p, v);
     return hipGetLastError();
@@ -1059,6 +1113,7 @@ namespace {
 TileJob index_job(const lj_index* idx) {
     TileJob j{};
     j.r = idx->r_dev;
+    j.rs = idx->rs_dev;
     j.leaves = idx->leaf_dev;
     j.root = idx->root;
     j.kind = job_kind(idx);
@@ -1085,9 +1140,10 @@ void launch_binned_search(const lj_index* idx, const uint64_t* keys, uint64_t m,
     const uint32_t nt = (uint32_t)num_tiles(m, (uint64_t)kBlock * kItems);
     const uint32_t per = (nt + kXcds - 1) / kXcds;
     hipLaunchKernelGGL((probe_binned_kernel<Leaf, kUnique, kItems, kSearch>), dim3(per * kXcds),
-                       dim3(kBlock), 0, stream, idx->r_dev, (const Leaf*)idx->leaf_dev,
-                       idx->root, idx->slots_dev, (uint32_t)idx->nslots, idx->gap,
-                       idx->buckets_dev, idx->hash_spk, keys, m, nt, per, res);
+                       dim3(kBlock), 0, stream, idx->r_dev, idx->rs_dev,
+                       (const Leaf*)idx->leaf_dev, idx->root, idx->slots_dev,
+                       (uint32_t)idx->nslots, idx->gap, idx->buckets_dev, idx->hash_spk, keys,
+                       m, nt, per, res);
 }
 
 // Steps of the first pass of the two-pass gapped search, and keys per lane

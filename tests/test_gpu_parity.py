@@ -200,3 +200,18 @@ def test_device_windows_equal_host_windows():
             assert np.array_equal(pred.cpu().numpy(), pred_h)
             assert np.array_equal(lo.cpu().numpy(), lo_h)
             assert np.array_equal(hi.cpu().numpy(), hi_h)
+
+
+@pytest.mark.parametrize("n", [1, 15, 16, 17, 31, 32, 33, 1000])
+def test_windows_around_line_boundaries(n):
+    # The binary search reads one key per 16-key line of R first, then the
+    # candidate positions inside one line: every key of R, every gap
+    # between keys and both ends, with one leaf (window = all of R) and
+    # many, and FP32 / FP64 leaves.
+    R = np.arange(0, 3 * n, 3, dtype=np.uint64) + np.uint64(5)
+    S = np.arange(0, 3 * n + 9, dtype=np.uint64)
+    for leaves in (1, max(1, n // 4)):
+        for flags in FLAGS + [lj.LJ_LEAF_FP32 | BIN]:
+            assert_parity(R, S, leaves, flags, f"line boundaries n={n}")
+    D = np.repeat(R, 3)  # runs of three equal keys across line ends
+    assert_parity(D, S, 1, lj.LJ_LEAF_FP32, f"line boundaries dup n={n}")
