@@ -453,7 +453,11 @@ def main():
     achieved = alg / (kern_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": load_traffic(w.name, binned, args.index),
+            # The counter summaries were taken with FP32 leaves, binary search
+            # and the default slots per key.
+            "traffic": (load_traffic(w.name, binned, args.index)
+                        if args.leaf == "fp32" and args.search == "binary"
+                        and (args.index == "rmi" or args.slots_per_key == 4) else None),
             "algorithmic_bytes_per_launch": alg,
             "kernel": (("probe_binned_gapped_kernel+gapped_queue_kernel"
                         if gapped and st.max_mult <= 1 else "probe_binned_kernel")
