@@ -13,7 +13,9 @@
  *     { (s_idx, r_idx) : S[s_idx] == R[r_idx] }
  *
  * emitted in ascending (s_idx, r_idx) order, where r_idx is the position in
- * the sorted R and s_idx the position in S as passed.
+ * the sorted R and s_idx the position in S as passed.  Two more index kinds
+ * are built over the same RMI and give the same pairs: the gapped RMI
+ * (Section III-A) and the learned hash index (Section III-C).
  *
  * Conventions for every entry point:
  *   - Status codes are returned; nothing throws across this interface.
@@ -87,6 +89,10 @@ enum {
  *   stream       stream used for the uploads (the call returns after they
  *                complete).
  *   out_index    receives the new index; free it with lj_free_index.
+ *
+ * The index also keeps the first key of every 16-key (128-byte) line of R:
+ * the binary search first bisects these line samples inside the window,
+ * then the candidate positions of one line of R.
  *
  * Fitting: the root is an FP64 least-squares line from (key - R[0]) to
  * leaf coordinate i*leaves/n; each leaf is an FP64 least-squares line from
@@ -400,7 +406,8 @@ typedef struct {
                                  hash, the mean number of buckets a probe of
                                  a key of R reads) */
     uint64_t max_window;      /* largest search window of any leaf */
-    uint64_t device_bytes;    /* device memory held (R + leaf table) */
+    uint64_t device_bytes;    /* device memory held (R, line samples, leaves,
+                                 fences, and the slot or bucket arrays) */
     double root_a0, root_b0;  /* root model parameters */
     uint64_t root_kmin;       /* root model key origin (R[0]) */
     uint32_t slots_per_key;   /* gapped RMI or learned hash: slots per key of R

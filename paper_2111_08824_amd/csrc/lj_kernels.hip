@@ -10,9 +10,13 @@
 //   2. root model (FP64 fma) -> leaf record (32 or 48 bytes, read through
 //      L2/MALL) -> leaf model (FP32 fmaf or FP64 fma) -> window [lo, hi];
 //   3. lower_bound in R over the window, the kItems keys of a lane advanced
-//      in lockstep so that each lane keeps kItems independent loads in flight;
-//      the element found is the last one read with R[mid] >= x, so the
-//      equality test needs no extra load;
+//      in lockstep so that each lane keeps kItems independent loads in flight,
+//      in two stages (the window's line samples, one key per 128-byte line
+//      of R, then the candidate positions of one line); the element found is
+//      the last one read with value >= x, so the equality test needs no
+//      extra load.  On a gapped index the search gallops forward from the
+//      predicted slot instead, and on a learned hash index it walks the
+//      bucket chain;
 //   4. length of the run of equal keys (only when R has duplicates);
 //   5. tile-local exclusive offsets of the outputs: ballot/popcount per wave
 //      when every count is 0 or 1, an LDS scan otherwise;
