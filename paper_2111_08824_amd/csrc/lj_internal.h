@@ -139,6 +139,9 @@ __host__ __device__ inline uint64_t gapped_pred(const Leaf& lf, uint64_t x, uint
 // needs more registers).
 constexpr int kBlock = 256;
 constexpr uint32_t kLineKeys = 16;  // keys of R per 128-byte cache line (line samples)
+// The direct probe searches in two stages when the index's mean window is at
+// least this long (the binned probe always does).
+constexpr double kTwoStageMinWindow = 64.0;
 constexpr int kItemsUnique = 24;
 constexpr int kItemsDup = 16;
 constexpr int kItemsGapped = 8;

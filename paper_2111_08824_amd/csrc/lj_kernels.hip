@@ -102,12 +102,46 @@ __device__ void finish_tile(const TileJob& j) {
     }
 }
 
+// Lockstep lower_bound over array A for the kItems keys of a lane: key k
+// searches [first[k], first[k] + len[k]).  Finished keys re-read A[0] (a
+// cached line) so that the loop body has no branches and the loads of all
+// keys issue back to back.  On return first[k] is the range's end or the
+// position of the last element read with A[mid] >= x[k], and bit k of
+// eqmask tells whether that element equals x[k] (unchanged when no element
+// >= x[k] was read).
+template <int kItems>
+__device__ __forceinline__ void bisect_lockstep(const uint64_t* __restrict__ A,
+                                                const uint64_t (&x)[kItems],
+                                                uint32_t (&first)[kItems],
+                                                uint32_t (&len)[kItems], uint32_t& eqmask) {
+    for (;;) {
+        uint32_t anylen = 0;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) anylen |= len[k];
+        if (!anylen) break;
+        uint64_t v[kItems];
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) v[k] = A[len[k] ? first[k] + (len[k] >> 1) : 0];
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const uint32_t half = len[k] >> 1;
+            const uint32_t act = len[k] != 0 ? 1u : 0u;
+            const uint32_t lt = v[k] < x[k] ? act : 0u;   // act && lt
+            const uint32_t ge = act ^ lt;                   // act && !lt
+            const uint32_t eq = v[k] == x[k] ? 1u : 0u;
+            first[k] += lt * (half + 1);
+            eqmask = (eqmask & ~(ge << k)) | ((eq & ge) << k);
+            len[k] = lt ? len[k] - half - 1 : half;
+        }
+    }
+}
+
 // Steps 1-4 for the keys of one tile: kBlock threads, the first `kpl`
 // (<= kItems) keys of each lane are live; key k of thread t is
 // s[tbase + k*kBlock + t].  On return first[k] is the lower bound of the key
 // in R (inside its window) and c[k] the number of R keys equal to it (0 for
 // a miss or a key past the end of s).
-template <class Leaf, bool kUnique, int kItems, bool kExp>
+template <class Leaf, bool kUnique, int kItems, bool kExp, bool kTwoStage = true>
 __device__ __forceinline__ void search_keys(const uint64_t* __restrict__ R,
                                             const uint64_t* __restrict__ RS, const Leaf* leaves,
                                             const RootModel& root, const uint64_t* s,
@@ -218,34 +252,8 @@ __device__ __forceinline__ void search_keys(const uint64_t* __restrict__ R,
 #pragma unroll
         for (int k = 0; k < kItems; ++k) first[k] = (uint32_t)hi[k];
     } else {
-        // 3: lockstep lower_bound over the windows, in two stages (below).
-        // In each, finished keys re-read A[0] (a cached line) so that the
-        // loop body has no branches and the loads of all keys of the lane
-        // issue back to back.  When a stage ends, first[k] is its range's
-        // end or the position of the last element read with A[mid] >= x[k],
-        // so bit k of eqmask tells whether that element equals x[k].
-        auto bisect = [&](const uint64_t* __restrict__ A) {
-            for (;;) {
-                uint32_t anylen = 0;
-#pragma unroll
-                for (int k = 0; k < kItems; ++k) anylen |= len[k];
-                if (!anylen) break;
-                uint64_t v[kItems];
-#pragma unroll
-                for (int k = 0; k < kItems; ++k) v[k] = A[len[k] ? first[k] + (len[k] >> 1) : 0];
-#pragma unroll
-                for (int k = 0; k < kItems; ++k) {
-                    const uint32_t half = len[k] >> 1;
-                    const uint32_t act = len[k] != 0 ? 1u : 0u;
-                    const uint32_t lt = v[k] < x[k] ? act : 0u;   // act && lt
-                    const uint32_t ge = act ^ lt;                   // act && !lt
-                    const uint32_t eq = v[k] == x[k] ? 1u : 0u;
-                    first[k] += lt * (half + 1);
-                    eqmask = (eqmask & ~(ge << k)) | ((eq & ge) << k);
-                    len[k] = lt ? len[k] - half - 1 : half;
-                }
-            }
-        };
+        // 3: lockstep lower_bound over the windows (bisect_lockstep), in two
+        // stages (below).
         // Two stages.  The window [a, e) holds the line samples c0..c1
         // (positions kLineKeys*c in [a, e)); their lower bound i (c0..c1
         // + 1) leaves one candidate range: positions after sample i - 1
@@ -256,30 +264,34 @@ __device__ __forceinline__ void search_keys(const uint64_t* __restrict__ R,
         // per 128-byte line), so the first stage's reads stay in a
         // smaller, better-cached array and one line of R is read per
         // key.
-        uint32_t a[kItems], e[kItems];
+        // (The direct probe on an index with short windows searches R in
+        // one stage, which takes fewer steps there.)
+        if constexpr (kTwoStage) {
+            uint32_t a[kItems], e[kItems];
 #pragma unroll
-        for (int k = 0; k < kItems; ++k) {
-            a[k] = first[k];
-            e[k] = first[k] + len[k];
-            const uint32_t c0 = (a[k] + kLineKeys - 1) / kLineKeys;
-            const uint32_t c1 = len[k] ? (e[k] - 1) / kLineKeys : 0u;
-            const bool some = len[k] != 0 && c1 >= c0;
-            first[k] = c0;
-            len[k] = some ? c1 - c0 + 1 : 0u;
-        }
-        bisect(RS);
+            for (int k = 0; k < kItems; ++k) {
+                a[k] = first[k];
+                e[k] = first[k] + len[k];
+                const uint32_t c0 = (a[k] + kLineKeys - 1) / kLineKeys;
+                const uint32_t c1 = len[k] ? (e[k] - 1) / kLineKeys : 0u;
+                const bool some = len[k] != 0 && c1 >= c0;
+                first[k] = c0;
+                len[k] = some ? c1 - c0 + 1 : 0u;
+            }
+            bisect_lockstep<kItems>(RS, x, first, len, eqmask);
 #pragma unroll
-        for (int k = 0; k < kItems; ++k) {
-            const uint32_t i = first[k];
-            const uint32_t c0 = (a[k] + kLineKeys - 1) / kLineKeys;
-            const bool past = e[k] <= i * kLineKeys;  // no sample >= x in the window
-            const uint32_t lo = i == c0 ? a[k] : i * kLineKeys - (kLineKeys - 1);
-            const uint32_t hi = past ? e[k] : i * kLineKeys;
-            eqmask &= ~((past ? 1u : 0u) << k);
-            first[k] = lo;
-            len[k] = e[k] > a[k] ? hi - lo : 0u;
+            for (int k = 0; k < kItems; ++k) {
+                const uint32_t i = first[k];
+                const uint32_t c0 = (a[k] + kLineKeys - 1) / kLineKeys;
+                const bool past = e[k] <= i * kLineKeys;  // no sample >= x in the window
+                const uint32_t lo = i == c0 ? a[k] : i * kLineKeys - (kLineKeys - 1);
+                const uint32_t hi = past ? e[k] : i * kLineKeys;
+                eqmask &= ~((past ? 1u : 0u) << k);
+                first[k] = lo;
+                len[k] = e[k] > a[k] ? hi - lo : 0u;
+            }
         }
-        bisect(R);
+        bisect_lockstep<kItems>(R, x, first, len, eqmask);
     }
 
     // 4: run lengths.
@@ -681,6 +693,7 @@ constexpr int kSearchBinary = 0;
 constexpr int kSearchExp = 1;
 constexpr int kSearchGapped = 2;
 constexpr int kSearchHash = 3;
+constexpr int kSearchOneStage = 4;  // binary search of R without the line-sample stage
 
 // Probe one tile of a batch (steps 1-7).
 template <class Leaf, bool kUnique, int kItems, bool kWithOffsets, int kSearch>
@@ -697,7 +710,7 @@ __device__ __forceinline__ void probe_tile(const TileJob& j, const uint32_t tile
                                                   (const Leaf*)j.leaves, j.root, j.s, j.m,
                                                   (uint64_t)tile * kBlock * kpl, kpl, first, c);
     else
-        search_keys<Leaf, kUnique, kItems, kSearch == kSearchExp>(
+        search_keys<Leaf, kUnique, kItems, kSearch == kSearchExp, kSearch != kSearchOneStage>(
             j.r, j.rs, (const Leaf*)j.leaves, j.root, j.s, j.m, (uint64_t)tile * kBlock * kpl,
             kpl, first, c);
     emit_tile<kUnique, kItems, kWithOffsets>(j, tile, kpl, sh, first, c);
@@ -1136,6 +1149,14 @@ int search_mode(uint32_t kind) {
                                  : kSearchBinary;
 }
 
+// The direct probe's binary search: two stages unless the index's windows
+// are short.
+int direct_search_mode(const lj_index* idx, uint32_t kind) {
+    const int mode = search_mode(kind);
+    return mode == kSearchBinary && idx->mean_window < kTwoStageMinWindow ? kSearchOneStage
+                                                                           : mode;
+}
+
 template <class Leaf, bool kUnique, int kSearch>
 void launch_binned_search(const lj_index* idx, const uint64_t* keys, uint64_t m, void* res,
                           hipStream_t stream) {
@@ -1300,12 +1321,13 @@ hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m, lj_p
         if (e != hipSuccess) return e;
     }
     uint32_t* ctr = &hdr->tile_counter;
-    const int search = search_mode(kind);
-#define LJ_ITEMS(K)                                                                    \
-    e = search == kSearchHash     ? launch_probe_items<K, kSearchHash>(j, ctr, stream)   \
-        : search == kSearchGapped ? launch_probe_items<K, kSearchGapped>(j, ctr, stream) \
-        : search == kSearchExp    ? launch_probe_items<K, kSearchExp>(j, ctr, stream)    \
-                                  : launch_probe_items<K, kSearchBinary>(j, ctr, stream)
+    const int search = direct_search_mode(idx, kind);
+#define LJ_ITEMS(K)                                                                      \
+    e = search == kSearchHash       ? launch_probe_items<K, kSearchHash>(j, ctr, stream)   \
+        : search == kSearchGapped   ? launch_probe_items<K, kSearchGapped>(j, ctr, stream) \
+        : search == kSearchExp      ? launch_probe_items<K, kSearchExp>(j, ctr, stream)    \
+        : search == kSearchOneStage ? launch_probe_items<K, kSearchOneStage>(j, ctr, stream) \
+                                    : launch_probe_items<K, kSearchBinary>(j, ctr, stream)
     switch (kpl) {
         case 4: LJ_ITEMS(4); break;
         case 8: LJ_ITEMS(8); break;
