@@ -10,7 +10,9 @@ The join result has a plain definition (Section II-A, INLJ; Section VI-B,
     P = {(i, j) : S[i] == R[j]}  in lexicographic (i, j) order,  count = |P|.
 
 The learned index (Section II-D, RMI; Section III) only changes how fast P is
-found, never P itself.  ``oracle.c`` computes P three independent ways; see
+found, never P itself.  The learned sort join (Section IV) takes R in any
+order; its P is the same with j the position in R as given (``sort_join``),
+and its sorted relations are the (key, position) order (``sort_positions``).  ``oracle.c`` computes P three independent ways; see
 its header.  Parity of the model parameters themselves (slopes, intercepts,
 bound widths) is unpinned: the paper prints no values for them.
 """
@@ -51,7 +53,9 @@ def _L():
         cp = ctypes.POINTER(ctypes.c_uint64)
         L.orc_is_nondecreasing.argtypes = [vp, u64]
         L.orc_is_nondecreasing.restype = ctypes.c_int
-        for f in (L.orc_brute_join, L.orc_sort_merge_join):
+        L.orc_sort_positions.argtypes = [vp, u64, vp, vp]
+        L.orc_sort_positions.restype = ctypes.c_int
+        for f in (L.orc_brute_join, L.orc_sort_merge_join, L.orc_sort_join):
             f.argtypes = [vp, u64, vp, u64, pp, cp]
             f.restype = ctypes.c_int
         L.orc_equal_range.argtypes = [vp, u64, vp, u64, vp, vp]
@@ -100,6 +104,23 @@ def brute_join(R, S) -> np.ndarray:
 def sort_merge_join(R, S) -> np.ndarray:
     """(k, 2) uint32 array of (s_idx, r_idx) pairs by sort-merge."""
     return _join(_L().orc_sort_merge_join, R, S)
+
+
+def sort_join(R, S) -> np.ndarray:
+    """(k, 2) uint32 array of (s_idx, r_idx) pairs for R in any order
+    (r_idx = position in R as given), by sorting both sides and merging."""
+    return _join(_L().orc_sort_join, R, S)
+
+
+def sort_positions(keys):
+    """(sorted keys, input positions) in ascending (key, position) order."""
+    keys = _u64(keys)
+    out_k = np.empty(len(keys), dtype=np.uint64)
+    out_p = np.empty(len(keys), dtype=np.uint32)
+    if len(keys) and _L().orc_sort_positions(keys.ctypes.data, len(keys), out_k.ctypes.data,
+                                             out_p.ctypes.data):
+        raise MemoryError("oracle sort ran out of host memory")
+    return out_k, out_p
 
 
 def equal_range(R, keys):

@@ -21,6 +21,13 @@
  *   orc_equal_range      textbook lower/upper-bound binary search on the
  *                        sorted R for single keys (sampled checks at sizes
  *                        where a full join is too slow on the host).
+ *
+ * For the learned sort join (Section IV) R comes in any order and j is its
+ * position as given; the result is the same P:
+ *   orc_sort_join        sort (key, position) pairs of both relations with
+ *                        qsort, merge, emit, counting sort by i.
+ *   orc_sort_positions   the sorted (key, position) pairs of one relation.
+ * orc_brute_join takes R in any order and pins both.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -127,6 +134,97 @@ int orc_sort_merge_join(const uint64_t *R, uint64_t n, const uint64_t *S,
     free(T);
 
     /* Stable counting sort by i. */
+    uint64_t *start = (uint64_t *)calloc(m + 1, sizeof(uint64_t));
+    uint32_t *sorted = (uint32_t *)malloc((v.len ? v.len : 1) * 2 * sizeof(uint32_t));
+    if (!start || !sorted) { free(start); free(sorted); free(v.p); return -1; }
+    for (uint64_t k = 0; k < v.len; ++k) start[v.p[2 * k] + 1]++;
+    for (uint64_t i = 0; i < m; ++i) start[i + 1] += start[i];
+    for (uint64_t k = 0; k < v.len; ++k) {
+        uint64_t dst = start[v.p[2 * k]]++;
+        sorted[2 * dst] = v.p[2 * k];
+        sorted[2 * dst + 1] = v.p[2 * k + 1];
+    }
+    free(start);
+    free(v.p);
+    *out_pairs = sorted;
+    *out_count = v.len;
+    return 0;
+}
+
+/*
+ * (key, position) pairs of keys[0..n) in ascending (key, position) order,
+ * by qsort: the sorted relation a sort-based join produces from an
+ * unsorted input (Section IV-C), with each key's input position carried.
+ * Returns 0, or -1 on allocation failure.
+ */
+int orc_sort_positions(const uint64_t *keys, uint64_t n, uint64_t *out_keys,
+                       uint32_t *out_pos) {
+    orc_kv *T = (orc_kv *)malloc((n ? n : 1) * sizeof(orc_kv));
+    if (!T) return -1;
+    for (uint64_t j = 0; j < n; ++j) {
+        T[j].key = keys[j];
+        T[j].idx = j;
+    }
+    qsort(T, n, sizeof(orc_kv), cmp_kv);
+    for (uint64_t j = 0; j < n; ++j) {
+        out_keys[j] = T[j].key;
+        out_pos[j] = (uint32_t)T[j].idx;
+    }
+    free(T);
+    return 0;
+}
+
+/*
+ * The join of two unsorted relations (Section IV, learned sort join): the
+ * same P = {(i, j) : S[i] == R[j]} in (i, j) order, where j is the position
+ * in R as given.
+ *   1. U = [(R[j], j)] and T = [(S[i], i)], each sorted by (key, position).
+ *   2. Merge U and T; on a key present in both, emit (T[k].idx, U[l].idx)
+ *      for every copy on each side (U's copies in ascending j).
+ *   3. Stable counting sort of the pairs by i.
+ * Returns 0, or -1 on allocation failure.
+ */
+int orc_sort_join(const uint64_t *R, uint64_t n, const uint64_t *S, uint64_t m,
+                  uint32_t **out_pairs, uint64_t *out_count) {
+    *out_pairs = NULL;
+    *out_count = 0;
+    orc_kv *U = (orc_kv *)malloc((n ? n : 1) * sizeof(orc_kv));
+    orc_kv *T = (orc_kv *)malloc((m ? m : 1) * sizeof(orc_kv));
+    if (!U || !T) { free(U); free(T); return -1; }
+    for (uint64_t j = 0; j < n; ++j) {
+        U[j].key = R[j];
+        U[j].idx = j;
+    }
+    for (uint64_t i = 0; i < m; ++i) {
+        T[i].key = S[i];
+        T[i].idx = i;
+    }
+    qsort(U, n, sizeof(orc_kv), cmp_kv);
+    qsort(T, m, sizeof(orc_kv), cmp_kv);
+
+    pairvec v = {0, 0, 0};
+    uint64_t a = 0, b = 0;
+    while (a < m && b < n) {
+        if (T[a].key < U[b].key) {
+            ++a;
+        } else if (U[b].key < T[a].key) {
+            ++b;
+        } else {
+            uint64_t key = U[b].key, a2 = a, b2 = b;
+            while (a2 < m && T[a2].key == key) ++a2;
+            while (b2 < n && U[b2].key == key) ++b2;
+            for (uint64_t k = a; k < a2; ++k)
+                for (uint64_t l = b; l < b2; ++l)
+                    if (push(&v, T[k].idx, U[l].idx)) {
+                        free(v.p); free(T); free(U); return -1;
+                    }
+            a = a2;
+            b = b2;
+        }
+    }
+    free(T);
+    free(U);
+
     uint64_t *start = (uint64_t *)calloc(m + 1, sizeof(uint64_t));
     uint32_t *sorted = (uint32_t *)malloc((v.len ? v.len : 1) * 2 * sizeof(uint32_t));
     if (!start || !sorted) { free(start); free(sorted); free(v.p); return -1; }
