@@ -507,10 +507,63 @@ int lj_hash_buckets_host(const lj_index* index, uint64_t* keys_host,
                          uint64_t* nprimary_out);
 
 /*
- * Timing hook for benchmarks: the next lj_probe_join or lj_probe_join_async
- * call made by this host thread records `start` immediately before and
- * `stop` immediately after its probe kernel (with LJ_PROBE_BINNED: the
- * search kernel over the partitioned keys), on the call's stream.  Pass
+ * Learned sort join (Section IV): the join of two relations in any order,
+ *
+ *     { (s_idx, r_idx) : S[s_idx] == R[r_idx] }
+ *
+ * in ascending (s_idx, r_idx) order, with r_idx and s_idx the positions in
+ * R and S as passed (no index is built beforehand).  The phases follow
+ * Section IV-B..D: a CDF model of R from a sorted sample (a linear spline
+ * over equi-depth sample knots), range partitioning of R by the model
+ * scaled up (histograms, prefix sums, stable scatter passes), a bitonic
+ * sort of each partition (Section IV-C), and a join in which each key of S
+ * is looked up in the one partition of the sorted R its key maps to
+ * (Section IV-D).  Asynchronous; nothing is allocated, so calls can be
+ * captured in a HIP graph.
+ *
+ *   r_keys_dev    n keys of R in device memory, n < 2^31.
+ *   s_keys_dev    m keys of S in device memory, m < 2^32.
+ *   out_pairs_dev room for out_capacity pairs, or NULL with capacity 0
+ *                 (count only).  Capacity protocol of lj_probe_join_async.
+ *   out_count_dev device uint64 receiving the total pair count, or
+ *                 UINT64_MAX if a kernel hit its internal wait bound.
+ *   workspace_dev caller-owned device scratch of at least
+ *                 lj_sort_join_workspace_bytes(n, m) bytes (about
+ *                 40 n + 32 m bytes), 256-byte aligned; calls sharing one
+ *                 workspace must be ordered on one stream.
+ *
+ * The benchmark timing hook (lj_probe_set_timing_events) brackets the join
+ * kernel over the partitioned S.  Errors (host-side checks only):
+ * LJ_ERR_ARG, LJ_ERR_TOO_LARGE, LJ_ERR_WORKSPACE, LJ_ERR_DEVICE.
+ */
+uint64_t lj_sort_join_workspace_bytes(uint64_t n, uint64_t m);
+int lj_sort_join_async(const uint64_t* r_keys_dev, uint64_t n,
+                       const uint64_t* s_keys_dev, uint64_t m,
+                       lj_pair* out_pairs_dev, uint64_t out_capacity,
+                       uint64_t* out_count_dev, void* workspace_dev,
+                       uint64_t workspace_bytes, hipStream_t stream);
+
+/*
+ * The sort phase of the learned sort join on its own (Section IV-B and
+ * IV-C): keys_dev (n keys, any order) into sorted_keys_dev and, for each
+ * output slot, the input position of its key in positions_dev, in
+ * ascending (key, position) order.  Workspace: at least
+ * lj_sort_join_workspace_bytes(n, 0) bytes, 256-byte aligned.  Output
+ * buffers are caller-owned and must not overlap keys_dev.  Asynchronous.
+ * Errors: LJ_ERR_ARG, LJ_ERR_TOO_LARGE (n >= 2^31), LJ_ERR_WORKSPACE,
+ * LJ_ERR_DEVICE.
+ */
+int lj_learned_sort_async(const uint64_t* keys_dev, uint64_t n,
+                          uint64_t* sorted_keys_dev, uint32_t* positions_dev,
+                          void* workspace_dev, uint64_t workspace_bytes,
+                          hipStream_t stream);
+
+/*
+ * Timing hook for benchmarks: the next lj_probe_join, lj_probe_join_async or
+ * lj_sort_join_async call made by this host thread records `start`
+ * immediately before and `stop` immediately after its probe kernel (with
+ * LJ_PROBE_BINNED: the search kernel over the partitioned keys; for the
+ * sort join: its join kernel), on the call's stream.  Pass
  * NULL events to disable.
  */
 int lj_probe_set_timing_events(hipEvent_t start, hipEvent_t stop);

@@ -313,6 +313,38 @@ int lj_probe_join(const lj_index* idx, const uint64_t* s, uint64_t m, lj_pair* o
     return (out && total > cap) ? LJ_ERR_CAPACITY : LJ_OK;
 }
 
+uint64_t lj_sort_join_workspace_bytes(uint64_t n, uint64_t m) {
+    return lj::sort_join_ws(n, m).total;
+}
+
+int lj_learned_sort_async(const uint64_t* keys, uint64_t n, uint64_t* keys_out,
+                          uint32_t* pos_out, void* ws, uint64_t ws_bytes, hipStream_t stream) {
+    if (n > 0 && (!keys || !keys_out || !pos_out)) return LJ_ERR_ARG;
+    if (n >= kMaxN) return LJ_ERR_TOO_LARGE;
+    if (n == 0) return LJ_OK;
+    const lj::SortJoinWs L = lj::sort_join_ws(n, 0);
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < L.total) return LJ_ERR_WORKSPACE;
+    return lj::launch_learned_sort(keys, n, keys_out, pos_out, ws, L, stream) == hipSuccess
+               ? LJ_OK
+               : LJ_ERR_DEVICE;
+}
+
+int lj_sort_join_async(const uint64_t* r, uint64_t n, const uint64_t* s, uint64_t m,
+                       lj_pair* out, uint64_t cap, uint64_t* count_dev, void* ws,
+                       uint64_t ws_bytes, hipStream_t stream) {
+    hipEvent_t ev0 = t_ev_start, ev1 = t_ev_stop;
+    t_ev_start = t_ev_stop = nullptr;
+    if (!count_dev || (n > 0 && !r) || (m > 0 && !s) || (cap > 0 && !out)) return LJ_ERR_ARG;
+    if (n >= kMaxN || m >= kMaxM) return LJ_ERR_TOO_LARGE;
+    if (n > 0 && m > 0 &&
+        (!ws || ((uintptr_t)ws & 255) || ws_bytes < lj::sort_join_ws(n, m).total))
+        return LJ_ERR_WORKSPACE;
+    return lj::launch_sort_join(r, n, s, m, out, cap, count_dev, ws, stream, ev0, ev1) ==
+                   hipSuccess
+               ? LJ_OK
+               : LJ_ERR_DEVICE;
+}
+
 int lj_index_get_stats(const lj_index* idx, lj_index_stats* o) {
     if (!idx || !o) return LJ_ERR_ARG;
     o->n = idx->n;

@@ -365,6 +365,14 @@ hipError_t launch_partition(const lj_index* idx, const uint64_t* s, uint64_t m, 
     return hipGetLastError();
 }
 
+hipError_t launch_scan_u32(uint32_t* d, uint64_t n, uint64_t* status, uint32_t* ctr,
+                           uint32_t* err, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(scan_kernel<uint32_t>, dim3((unsigned)num_tiles(n, kScanTile)),
+                       dim3(kBlock), 0, stream, d, n, status, ctr, err);
+    return hipGetLastError();
+}
+
 hipError_t launch_unpermute(const uint32_t* dest, const void* in, void* out, uint64_t m,
                             bool wide, hipStream_t stream) {
     const uint32_t nchunks = (uint32_t)num_tiles(m, kPartChunk);

@@ -1,0 +1,625 @@
+// Learned sort join (Section IV) of an unsorted R with an unsorted S.
+//
+// Phases, after Section IV-B..D, on one GPU:
+//   model      (IV-B, "Model Building") a strided sample of R is sorted in
+//              one block's LDS; every kSjSamplesPerKnot-th sample is a knot
+//              of a linear-spline CDF, and a bucket table over the knots
+//              (the key bucket of lj_internal.h) locates a key's segment.
+//   partition  (IV-B, "Range Partitioning") the model, scaled up by `fan`
+//              sub-partitions per segment, gives each key its partition
+//              number (pid); per-chunk histograms, their prefix sums and
+//              sequential per-digit writes put R in pid order, one stable
+//              pass per 6-bit digit of the pid, carrying each key's input
+//              position.
+//   sort       (IV-C) each partition is sorted on its own by a bitonic
+//              network over (key, position) in LDS; since the pids are
+//              monotone in the key, R is then globally sorted.
+//   join       (IV-D) S is put in order of its pid's high digits by two
+//              more passes, and each key of S looks up its run in the one
+//              partition of the sorted R that can hold its key (the
+//              chunked join's overlap range for a shared model); the runs
+//              are put back in S order and emitted, positions mapped back
+//              to R's input order.
+#include <hip/hip_runtime.h>
+
+#include "lj_device.h"
+#include "lj_internal.h"
+
+namespace lj {
+namespace {
+
+constexpr int kWaves = kBlock / 64;
+constexpr uint32_t kWaveSpan = kPartChunk / kWaves;
+constexpr int kModelThreads = 1024;
+constexpr int kBigThreads = 1024;
+constexpr int kJoinItems = 8;
+
+__device__ inline uint32_t sj_digit(uint32_t pid, uint32_t shift) {
+    return (pid >> shift) & (kDigits - 1);
+}
+
+// (key, position) order.
+__device__ inline bool sj_greater(uint64_t ka, uint32_t pa, uint64_t kb, uint32_t pb) {
+    return ka > kb || (ka == kb && pa > pb);
+}
+
+// Sample knot t of nk + 1 (equi-depth over the sorted sample s[0..ns)).
+__device__ inline uint32_t sj_knot_at(uint32_t t, uint32_t ns, uint32_t nk) {
+    return (uint32_t)(((uint64_t)t * (ns - 1)) / nk);
+}
+
+// Model of R: sample ns keys at stride n / ns, sort them, write the nk + 1
+// knots and, per key bucket b, the number of knots in lower buckets.
+__global__ __launch_bounds__(kModelThreads) void sj_model_kernel(
+    const uint64_t* __restrict__ keys, uint64_t n, uint32_t ns, uint32_t nk,
+    uint64_t* __restrict__ knots, uint16_t* __restrict__ kb_lo) {
+    __shared__ uint64_t s[kSjSamples];
+    const uint32_t tid = threadIdx.x;
+    uint32_t N = 1;
+    while (N < ns) N <<= 1;
+    for (uint32_t i = tid; i < N; i += kModelThreads)
+        s[i] = i < ns ? keys[((uint64_t)i * n) / ns] : ~0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= N; k <<= 1) {
+        for (uint32_t d = k >> 1; d > 0; d >>= 1) {
+            for (uint32_t c = tid; c < N / 2; c += kModelThreads) {
+                const uint32_t a = 2 * c - (c & (d - 1));
+                const uint32_t b = a + d;
+                const bool up = (a & k) == 0;
+                const uint64_t x = s[a], y = s[b];
+                if ((x > y) == up) {
+                    s[a] = y;
+                    s[b] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t t = tid; t <= nk; t += kModelThreads) knots[t] = s[sj_knot_at(t, ns, nk)];
+    // kb_lo[b] = t for the buckets b in (bucket(knot t-1), bucket(knot t)].
+    for (uint32_t t = tid; t <= nk + 1; t += kModelThreads) {
+        const int hi = t <= nk ? (int)key_bucket(s[sj_knot_at(t, ns, nk)]) : (int)kBuckets;
+        const int lo = t ? (int)key_bucket(s[sj_knot_at(t - 1, ns, nk)]) : -1;
+        for (int b = lo + 1; b <= hi; ++b) kb_lo[b] = (uint16_t)t;
+    }
+}
+
+// Partition number of key x: below the first knot and from the last knot on
+// by key bucket distance, inside segment [k0, k1) by linear interpolation.
+// Non-decreasing in x.
+__device__ inline uint32_t sj_pid(uint64_t x, const uint64_t* kn, const uint16_t* kl,
+                                  uint32_t nk, uint32_t fan) {
+    const uint32_t bk = key_bucket(x);
+    uint32_t b = kl[bk], len = kl[bk + 1] - kl[bk];
+    while (len) {
+        const uint32_t half = len >> 1, at = b + half;
+        if (kn[at] <= x) {
+            b = at + 1;
+            len -= half + 1;
+        } else {
+            len = half;
+        }
+    }
+    // b = number of knots <= x.
+    if (b == 0) {
+        const uint32_t d = key_bucket(kn[0]) - bk;
+        return fan - 1 - (d < fan - 1 ? d : fan - 1);
+    }
+    if (b > nk) {
+        const uint32_t d = bk - key_bucket(kn[nk]);
+        return (nk + 1) * fan + (d < fan - 1 ? d : fan - 1);
+    }
+    const uint64_t k0 = kn[b - 1], k1 = kn[b];
+    const double frac = (double)(x - k0) / (double)(k1 - k0);
+    uint32_t sub = (uint32_t)(frac * (double)fan);
+    sub = sub < fan ? sub : fan - 1;
+    return b * fan + sub;
+}
+
+// Per chunk of kPartChunk keys: histogram of the pid digit at `shift`
+// into hist[digit * nchunks + chunk].  With kFromKeys the pids are computed
+// by the model (knots and bucket table staged in LDS) and stored to pids.
+template <bool kFromKeys>
+__global__ __launch_bounds__(kBlock) void sj_hist_kernel(
+    const uint64_t* __restrict__ keys, const uint64_t* __restrict__ knots,
+    const uint16_t* __restrict__ kb_lo, uint32_t nk, uint32_t fan,
+    uint32_t* __restrict__ pids, uint64_t m, uint32_t nchunks, uint32_t shift,
+    uint32_t* __restrict__ hist) {
+    __shared__ uint64_t sk[kFromKeys ? kSjMaxSegments + 1 : 1];
+    __shared__ uint16_t sl[kFromKeys ? kBuckets + 1 : 1];
+    __shared__ uint32_t cnt[kDigits];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if constexpr (kFromKeys) {
+        for (uint32_t i = tid; i <= nk; i += kBlock) sk[i] = knots[i];
+        for (uint32_t i = tid; i <= kBuckets; i += kBlock) sl[i] = kb_lo[i];
+    }
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        if (tid < (int)kDigits) cnt[tid] = 0;
+        __syncthreads();
+        const uint64_t e0 = (uint64_t)c * kPartChunk + (uint64_t)wave * kWaveSpan + lane;
+#pragma unroll
+        for (int k = 0; k < (int)kPartItems; ++k) {
+            const uint64_t p = e0 + (uint64_t)k * 64;
+            if (p < m) {
+                uint32_t pid;
+                if constexpr (kFromKeys) {
+                    pid = sj_pid(keys[p], sk, sl, nk, fan);
+                    pids[p] = pid;
+                } else {
+                    pid = pids[p];
+                }
+                atomicAdd(&cnt[sj_digit(pid, shift)], 1u);
+            }
+        }
+        __syncthreads();
+        if (tid < (int)kDigits) hist[(uint64_t)tid * nchunks + c] = cnt[tid];
+        __syncthreads();
+    }
+}
+
+// One stable partition pass by pid digit (pid >> shift) & 63; gofs holds
+// the scanned digit-major counts of sj_hist_kernel for the same chunks.
+// Moves keys and pids; with kPos also the input positions (pos_in null:
+// the element's own index); with kDest stores dest_out[p] = output
+// position of input p.
+template <bool kPos, bool kDest>
+__global__ __launch_bounds__(kBlock) void sj_scatter_kernel(
+    const uint64_t* __restrict__ keys_in, const uint32_t* __restrict__ pids_in,
+    const uint32_t* __restrict__ pos_in, const uint32_t* __restrict__ gofs, uint64_t m,
+    uint32_t nchunks, uint32_t shift, uint64_t* __restrict__ keys_out,
+    uint32_t* __restrict__ pids_out, uint32_t* __restrict__ pos_out,
+    uint32_t* __restrict__ dest_out) {
+    __shared__ uint64_t skey[kPartChunk];
+    __shared__ uint32_t spid[kPartChunk];
+    __shared__ uint32_t spos[kPos ? kPartChunk : 1];
+    __shared__ uint32_t wbase[kWaves][kDigits];
+    __shared__ uint32_t lstart[kDigits];
+    __shared__ uint32_t gstart[kDigits];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const uint64_t c0 = (uint64_t)c * kPartChunk;
+        const uint32_t e0 = (uint32_t)wave * kWaveSpan + lane;
+        uint64_t x[kPartItems];
+        uint32_t b[kPartItems], rank[kPartItems], ps[kPartItems];
+#pragma unroll
+        for (int k = 0; k < (int)kPartItems; ++k) {
+            const uint64_t p = c0 + e0 + (uint64_t)k * 64;
+            const uint64_t q = p < m ? p : m - 1;
+            x[k] = keys_in[q];
+            b[k] = pids_in[q];
+            if constexpr (kPos) ps[k] = pos_in ? pos_in[q] : (uint32_t)q;
+        }
+        uint32_t run = 0;
+#pragma unroll
+        for (int k = 0; k < (int)kPartItems; ++k) {
+            const bool valid = c0 + e0 + (uint64_t)k * 64 < m;
+            const uint32_t dg = sj_digit(b[k], shift);
+            const uint64_t vb = __ballot(valid);
+            uint64_t same = vb, mine = vb;
+#pragma unroll
+            for (int bit = 0; bit < (int)kDigitBits; ++bit) {
+                const uint64_t bb = __ballot((dg >> bit) & 1u);
+                same &= ((dg >> bit) & 1u) ? bb : ~bb;
+                mine &= ((lane >> bit) & 1) ? bb : ~bb;
+            }
+            rank[k] = (uint32_t)__shfl((int)run, (int)dg, 64) + (uint32_t)__popcll(same & lt);
+            run += (uint32_t)__popcll(mine);
+        }
+        wbase[wave][lane] = run;
+        __syncthreads();
+        if (wave == 0) {
+            uint32_t t[kWaves], tot = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                t[w] = wbase[w][lane];
+                tot += t[w];
+            }
+            const uint32_t excl = (uint32_t)wave_incl_scan(tot, lane) - tot;
+            lstart[lane] = excl;
+            uint32_t acc = excl;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                wbase[w][lane] = acc;
+                acc += t[w];
+            }
+            gstart[lane] = gofs[(uint64_t)lane * nchunks + c];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < (int)kPartItems; ++k) {
+            const uint64_t p = c0 + e0 + (uint64_t)k * 64;
+            if (p < m) {
+                const uint32_t dg = sj_digit(b[k], shift);
+                const uint32_t lpos = wbase[wave][dg] + rank[k];
+                skey[lpos] = x[k];
+                spid[lpos] = b[k];
+                if constexpr (kPos) spos[lpos] = ps[k];
+                if constexpr (kDest) dest_out[p] = gstart[dg] + (lpos - lstart[dg]);
+            }
+        }
+        __syncthreads();
+        const uint32_t nvalid = m - c0 < kPartChunk ? (uint32_t)(m - c0) : kPartChunk;
+        for (uint32_t lp = tid; lp < nvalid; lp += kBlock) {
+            const uint32_t pid = spid[lp];
+            const uint32_t dg = sj_digit(pid, shift);
+            const uint32_t dst = gstart[dg] + (lp - lstart[dg]);
+            keys_out[dst] = skey[lp];
+            pids_out[dst] = pid;
+            if constexpr (kPos) pos_out[dst] = spos[lp];
+        }
+        __syncthreads();
+    }
+}
+
+// start[p] = first position of partition p in the pid-ordered R (p <= parts;
+// start[parts] = n), from the sorted pids.
+__global__ void sj_bounds_kernel(const uint32_t* __restrict__ pids, uint64_t n, uint32_t parts,
+                                 uint32_t* __restrict__ start) {
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j <= n;
+         j += (uint64_t)gridDim.x * blockDim.x) {
+        const int64_t prev = j == 0 ? -1 : (int64_t)pids[j - 1];
+        const int64_t cur = j == n ? (int64_t)parts : (int64_t)pids[j];
+        for (int64_t p = prev + 1; p <= cur; ++p) start[p] = (uint32_t)j;
+    }
+}
+
+// Compare-exchange (i, j), i < j, into ascending (key, position) order.
+template <class K, class P>
+__device__ inline void sj_cmpx(K* key, P* pos, uint32_t i, uint32_t j) {
+    const uint64_t ki = key[i], kj = key[j];
+    const uint32_t pi = pos[i], pj = pos[j];
+    if (sj_greater(ki, pi, kj, pj)) {
+        key[i] = kj;
+        key[j] = ki;
+        pos[i] = pj;
+        pos[j] = pi;
+    }
+}
+
+// Bitonic sort of key/pos[0..sz) by threads [0, nthreads): the network for
+// the next power of two N, every comparator ascending (the first step of
+// each stage compares mirrored elements), so that the elements past sz act
+// as +infinity and every comparator reaching them can be skipped.
+template <class K, class P>
+__device__ void sj_bitonic(K* key, P* pos, uint32_t sz, uint32_t tid, uint32_t nthreads) {
+    uint32_t N = 2;
+    while (N < sz) N <<= 1;
+    for (uint32_t k = 2; k <= N; k <<= 1) {
+        const uint32_t h = k >> 1;
+        for (uint32_t c = tid; c < N / 2; c += nthreads) {
+            const uint32_t blk = c / h, off = c & (h - 1);
+            const uint32_t i = blk * k + off, j = blk * k + k - 1 - off;
+            if (j < sz) sj_cmpx(key, pos, i, j);
+        }
+        __syncthreads();
+        for (uint32_t d = k >> 2; d > 0; d >>= 1) {
+            for (uint32_t c = tid; c < N / 2; c += nthreads) {
+                const uint32_t i = 2 * c - (c & (d - 1)), j = i + d;
+                if (j < sz) sj_cmpx(key, pos, i, j);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Sort every partition of at most kSjSortCap keys in LDS; queue the larger
+// ones for sj_sort_big_kernel.
+__global__ __launch_bounds__(kBlock) void sj_sort_kernel(uint64_t* __restrict__ keys,
+                                                         uint32_t* __restrict__ pos,
+                                                         const uint32_t* __restrict__ start,
+                                                         uint32_t parts,
+                                                         uint32_t* __restrict__ big) {
+    __shared__ uint64_t sk[kSjSortCap];
+    __shared__ uint32_t sp[kSjSortCap];
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t p = blockIdx.x; p < parts; p += gridDim.x) {
+        const uint32_t a = start[p], sz = start[p + 1] - a;
+        if (sz <= 1) continue;
+        if (sz > kSjSortCap) {
+            if (tid == 0) big[1 + atomicAdd(&big[0], 1u)] = p;
+            continue;
+        }
+        for (uint32_t i = tid; i < sz; i += kBlock) {
+            sk[i] = keys[a + i];
+            sp[i] = pos[a + i];
+        }
+        __syncthreads();
+        sj_bitonic(sk, sp, sz, tid, kBlock);
+        for (uint32_t i = tid; i < sz; i += kBlock) {
+            keys[a + i] = sk[i];
+            pos[a + i] = sp[i];
+        }
+        __syncthreads();
+    }
+}
+
+// Partitions larger than LDS: one block each, in global memory; a
+// partition already in (key, position) order (e.g. one repeated key, kept
+// in input order by the stable passes) is left as is.
+__global__ __launch_bounds__(kBigThreads) void sj_sort_big_kernel(
+    uint64_t* __restrict__ keys, uint32_t* __restrict__ pos,
+    const uint32_t* __restrict__ start, const uint32_t* __restrict__ big) {
+    __shared__ int unsorted;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nbig = big[0];
+    for (uint32_t q = blockIdx.x; q < nbig; q += gridDim.x) {
+        const uint32_t p = big[1 + q];
+        const uint32_t a = start[p], sz = start[p + 1] - a;
+        if (tid == 0) unsorted = 0;
+        __syncthreads();
+        int mine = 0;
+        for (uint32_t i = tid + 1; i < sz; i += kBigThreads)
+            mine |= sj_greater(keys[a + i - 1], pos[a + i - 1], keys[a + i], pos[a + i]) ? 1 : 0;
+        if (mine) atomicOr(&unsorted, 1);
+        __syncthreads();
+        const bool work = unsorted != 0;
+        __syncthreads();
+        if (work) sj_bitonic(keys + a, pos + a, sz, tid, kBigThreads);
+        __syncthreads();
+    }
+}
+
+// Join: S in coarse pid order, each key's run found by lower and upper
+// bound inside its own partition of the sorted R; res[q] = first position
+// | run length << 32, in the same order as the keys.  Blocks are mapped
+// XCD-contiguously so that one XCD's L2 serves neighbouring partitions.
+__global__ __launch_bounds__(kBlock) void sj_join_kernel(
+    const uint64_t* __restrict__ sk, const uint32_t* __restrict__ spid, uint64_t m,
+    const uint64_t* __restrict__ rk, const uint32_t* __restrict__ rstart, uint32_t ntiles,
+    uint32_t tiles_per_xcd, uint64_t* __restrict__ res) {
+    const uint32_t tile = (blockIdx.x % kXcds) * tiles_per_xcd + blockIdx.x / kXcds;
+    if (tile >= ntiles) return;
+    const uint64_t base = (uint64_t)tile * kBlock * kJoinItems + threadIdx.x;
+    uint64_t x[kJoinItems];
+    uint32_t b[kJoinItems], len[kJoinItems], hi[kJoinItems];
+#pragma unroll
+    for (int k = 0; k < kJoinItems; ++k) {
+        const uint64_t q = base + (uint64_t)k * kBlock;
+        const bool v = q < m;
+        x[k] = v ? sk[q] : 0;
+        const uint32_t p = v ? spid[q] : 0;
+        b[k] = v ? rstart[p] : 0;
+        hi[k] = v ? rstart[p + 1] : 0;
+        len[k] = hi[k] - b[k];
+    }
+    // Lower bound in lockstep.
+    for (;;) {
+        uint32_t act = 0;
+#pragma unroll
+        for (int k = 0; k < kJoinItems; ++k) act |= len[k];
+        if (!act) break;
+#pragma unroll
+        for (int k = 0; k < kJoinItems; ++k) {
+            if (len[k]) {
+                const uint32_t half = len[k] >> 1, at = b[k] + half;
+                if (rk[at] < x[k]) {
+                    b[k] = at + 1;
+                    len[k] -= half + 1;
+                } else {
+                    len[k] = half;
+                }
+            }
+        }
+    }
+    // Run end: usually the next key already differs; else an upper bound.
+    uint32_t e[kJoinItems];
+#pragma unroll
+    for (int k = 0; k < kJoinItems; ++k) {
+        const bool hit = b[k] < hi[k] && rk[b[k]] == x[k];
+        e[k] = hit ? b[k] + 1 : b[k];
+        len[k] = 0;
+        if (hit && e[k] < hi[k] && rk[e[k]] == x[k]) {
+            e[k] += 1;
+            len[k] = hi[k] - e[k];
+        }
+    }
+    for (;;) {
+        uint32_t act = 0;
+#pragma unroll
+        for (int k = 0; k < kJoinItems; ++k) act |= len[k];
+        if (!act) break;
+#pragma unroll
+        for (int k = 0; k < kJoinItems; ++k) {
+            if (len[k]) {
+                const uint32_t half = len[k] >> 1, at = e[k] + half;
+                if (rk[at] <= x[k]) {
+                    e[k] = at + 1;
+                    len[k] -= half + 1;
+                } else {
+                    len[k] = half;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kJoinItems; ++k) {
+        const uint64_t q = base + (uint64_t)k * kBlock;
+        if (q < m) res[q] = (uint64_t)b[k] | ((uint64_t)(e[k] - b[k]) << 32);
+    }
+}
+
+// Emitted r indices are positions in the sorted R: map them to R's input
+// positions (the written pairs only: min(total, cap)).
+__global__ void sj_map_kernel(lj_pair* __restrict__ out, uint64_t cap,
+                              const uint64_t* __restrict__ count,
+                              const uint32_t* __restrict__ rpos, uint64_t n) {
+    const uint64_t c = *count, lim = c < cap ? c : cap;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < lim;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t r = out[i].r_idx;
+        if (r < n) out[i].r_idx = rpos[r];
+    }
+}
+
+unsigned grid_of(uint64_t items, uint64_t cap) {
+    return (unsigned)(items == 0 ? 1 : items < cap ? items : cap);
+}
+
+// One relation into pid order: pids from the model, then one stable pass
+// per digit from `shift0` up.  Pass k reads the previous pass's output.
+struct PassBufs {
+    const uint64_t* keys_in;
+    uint64_t* keys[2];
+    uint32_t* pids[2];
+    uint32_t* pos[2];   // null: no positions carried
+    uint32_t* dest[2];  // null: no destinations stored
+    uint64_t* keys_last;
+    uint32_t* pos_last;
+};
+
+hipError_t partition_passes(const PassBufs& B, uint64_t n, uint32_t npass, uint32_t shift0,
+                            const SortJoinWs& L, char* w, uint32_t* hist, uint32_t st0,
+                            uint32_t ctr0, hipStream_t stream) {
+    const uint32_t nchunks = (uint32_t)num_tiles(n, kPartChunk);
+    const uint64_t nh = (uint64_t)kDigits * nchunks;
+    uint32_t* ctr = (uint32_t*)(w + L.scan_ctr);
+    uint32_t* err = &((WsHeader*)w)->err;
+    const uint64_t* knots = (const uint64_t*)(w + L.knots);
+    const uint16_t* kb_lo = (const uint16_t*)(w + L.kb_lo);
+    for (uint32_t k = 0; k < npass; ++k) {
+        const uint32_t shift = shift0 + k * kDigitBits;
+        uint32_t* pin = B.pids[k & 1];
+        if (k == 0)
+            hipLaunchKernelGGL(sj_hist_kernel<true>, dim3(grid_of(nchunks, 2048)), dim3(kBlock),
+                               0, stream, B.keys_in, knots, kb_lo, L.nk, L.fan, pin, n, nchunks,
+                               shift, hist);
+        else
+            hipLaunchKernelGGL(sj_hist_kernel<false>, dim3(grid_of(nchunks, 4096)),
+                               dim3(kBlock), 0, stream, (const uint64_t*)nullptr,
+                               (const uint64_t*)nullptr, (const uint16_t*)nullptr, 0u, 1u, pin,
+                               n, nchunks, shift, hist);
+        hipError_t e = launch_scan_u32(hist, nh, (uint64_t*)(w + L.scan_st[st0 + k]),
+                                       ctr + ctr0 + k, err, stream);
+        if (e != hipSuccess) return e;
+        const uint64_t* kin = k == 0 ? B.keys_in : B.keys[(k - 1) & 1];
+        const bool last = k + 1 == npass;
+        uint64_t* kout = last && B.keys_last ? B.keys_last : B.keys[k & 1];
+        uint32_t* pout = B.pos[0] ? (last && B.pos_last ? B.pos_last : B.pos[k & 1]) : nullptr;
+        const uint32_t* posin = k == 0 || !B.pos[0] ? nullptr : B.pos[(k - 1) & 1];
+        uint32_t* pidout = B.pids[(k + 1) & 1];
+        const dim3 grid(grid_of(nchunks, 65535)), block(kBlock);
+        if (B.pos[0])
+            hipLaunchKernelGGL((sj_scatter_kernel<true, false>), grid, block, 0, stream, kin, pin,
+                               posin, (const uint32_t*)hist, n, nchunks, shift, kout, pidout,
+                               pout, (uint32_t*)nullptr);
+        else
+            hipLaunchKernelGGL((sj_scatter_kernel<false, true>), grid, block, 0, stream, kin, pin,
+                               (const uint32_t*)nullptr, (const uint32_t*)hist, n, nchunks,
+                               shift, kout, pidout, (uint32_t*)nullptr, B.dest[k & 1]);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Sorted keys/positions of R end in (keys_out, pos_out); *rk/*rp/*rstart
+// receive where they are and the partition starts.
+hipError_t learned_sort(const uint64_t* keys, uint64_t n, uint64_t* keys_out, uint32_t* pos_out,
+                        char* w, const SortJoinWs& L, hipStream_t stream) {
+    hipLaunchKernelGGL(sj_model_kernel, dim3(1), dim3(kModelThreads), 0, stream, keys, n, L.ns,
+                       L.nk, (uint64_t*)(w + L.knots), (uint16_t*)(w + L.kb_lo));
+    PassBufs B{};
+    B.keys_in = keys;
+    for (int k = 0; k < 2; ++k) {
+        B.keys[k] = (uint64_t*)(w + L.r_keys[k]);
+        B.pids[k] = (uint32_t*)(w + L.r_bins[k]);
+        B.pos[k] = (uint32_t*)(w + L.r_pos[k]);
+    }
+    B.keys_last = keys_out;
+    B.pos_last = pos_out;
+    hipError_t e = partition_passes(B, n, L.rpasses, 0, L, w, (uint32_t*)(w + L.r_hist), 0, 0,
+                                    stream);
+    if (e != hipSuccess) return e;
+    const uint32_t* pids = B.pids[L.rpasses & 1];
+    uint32_t* start = (uint32_t*)(w + L.r_start);
+    hipLaunchKernelGGL(sj_bounds_kernel, dim3(grid_of(num_tiles(n + 1, kBlock), 8192)),
+                       dim3(kBlock), 0, stream, pids, n, L.parts, start);
+    uint32_t* big = (uint32_t*)(w + L.big_queue);
+    hipLaunchKernelGGL(sj_sort_kernel, dim3(grid_of(L.parts, 16384)), dim3(kBlock), 0, stream,
+                       keys_out, pos_out, (const uint32_t*)start, L.parts, big);
+    hipLaunchKernelGGL(sj_sort_big_kernel, dim3(256), dim3(kBigThreads), 0, stream, keys_out,
+                       pos_out, (const uint32_t*)start, (const uint32_t*)big);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_learned_sort(const uint64_t* keys, uint64_t n, uint64_t* keys_out,
+                               uint32_t* pos_out, void* ws, const SortJoinWs& L,
+                               hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    char* w = (char*)ws;
+    hipError_t e = launch_zero_words((uint64_t*)ws, L.ctrl_bytes / 8, stream);
+    if (e != hipSuccess) return e;
+    uint64_t* ko = keys_out ? keys_out : (uint64_t*)(w + L.r_keys[(L.rpasses - 1) & 1]);
+    uint32_t* po = pos_out ? pos_out : (uint32_t*)(w + L.r_pos[(L.rpasses - 1) & 1]);
+    return learned_sort(keys, n, ko, po, w, L, stream);
+}
+
+hipError_t launch_sort_join(const uint64_t* r, uint64_t n, const uint64_t* s, uint64_t m,
+                            lj_pair* out, uint64_t cap, uint64_t* count_dev, void* ws,
+                            hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
+    if (n == 0 || m == 0) return launch_set_u64(count_dev, 0, stream);
+    const SortJoinWs L = sort_join_ws(n, m);
+    char* w = (char*)ws;
+    hipError_t e = launch_zero_words((uint64_t*)ws, L.ctrl_bytes / 8, stream);
+    if (e != hipSuccess) return e;
+    // Sorted R in the workspace buffers of its last pass.
+    uint64_t* rk = (uint64_t*)(w + L.r_keys[(L.rpasses - 1) & 1]);
+    uint32_t* rp = (uint32_t*)(w + L.r_pos[(L.rpasses - 1) & 1]);
+    e = learned_sort(r, n, rk, rp, w, L, stream);
+    if (e != hipSuccess) return e;
+
+    // S into coarse pid order (two passes over the pid's high digits).
+    PassBufs B{};
+    B.keys_in = s;
+    for (int k = 0; k < 2; ++k) {
+        B.keys[k] = (uint64_t*)(w + L.s_keys[k]);
+        B.pids[k] = (uint32_t*)(w + L.s_bins[k]);
+        B.dest[k] = (uint32_t*)(w + L.s_dest[k]);
+    }
+    e = partition_passes(B, m, L.spasses, L.s_shift, L, w, (uint32_t*)(w + L.s_hist),
+                         kSjMaxPasses, kSjMaxPasses, stream);
+    if (e != hipSuccess) return e;
+    const uint64_t* sk = B.keys[1];
+    const uint32_t* spid = B.pids[0];
+    uint64_t* res2 = B.keys[0];  // dead after pass 2
+    uint64_t* res1 = B.keys[1];  // dead after the join
+    uint64_t* res0 = B.keys[0];  // res2 dead after the first put-back
+
+    if (ev0) {
+        e = hipEventRecord(ev0, stream);
+        if (e != hipSuccess) return e;
+    }
+    const uint32_t ntiles = (uint32_t)num_tiles(m, (uint64_t)kBlock * kJoinItems);
+    const uint32_t tpx = (uint32_t)num_tiles(ntiles, kXcds);
+    hipLaunchKernelGGL(sj_join_kernel, dim3(tpx * kXcds), dim3(kBlock), 0, stream, sk, spid, m,
+                       (const uint64_t*)rk, (const uint32_t*)(w + L.r_start), ntiles, tpx, res2);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ev1) {
+        e = hipEventRecord(ev1, stream);
+        if (e != hipSuccess) return e;
+    }
+
+    // Put the runs back in S order (pass 2, then pass 1), count per chunk,
+    // emit, map positions.
+    e = launch_unpermute(B.dest[1], res2, res1, m, true, stream);
+    if (e != hipSuccess) return e;
+    BinnedWs U{};
+    U.scan_ctr = L.scan_ctr + 32;  // its counter: word 2 from here
+    U.scan_st3 = L.scan_st[kSjMaxPasses + 2];
+    U.counts = L.counts;
+    e = launch_unpermute_count(B.dest[0], res1, res0, m, true, ws, U, stream);
+    if (e != hipSuccess) return e;
+    e = launch_emit_results(res0, m, (const uint64_t*)(w + L.counts), out, out ? cap : 0,
+                            count_dev, &((WsHeader*)ws)->err, stream);
+    if (e != hipSuccess) return e;
+    if (out && cap)
+        hipLaunchKernelGGL(sj_map_kernel, dim3(4096), dim3(kBlock), 0, stream, out, cap,
+                           (const uint64_t*)count_dev, (const uint32_t*)rp, n);
+    return hipGetLastError();
+}
+
+}  // namespace lj

@@ -42,6 +42,7 @@ EXPORTED = (
     "lj_server_submit_device", "lj_server_wait", "lj_server_get_stats", "lj_server_destroy",
     "lj_build_gapped_rmi", "lj_build_gapped_rmi_host_only", "lj_gapped_slots_host",
     "lj_build_learned_hash", "lj_build_learned_hash_host_only", "lj_hash_buckets_host",
+    "lj_sort_join_workspace_bytes", "lj_sort_join_async", "lj_learned_sort_async",
 )
 GAP_SLOT = 0xFFFFFFFF  # payload of a gap slot in lj_gapped_slots_host
 
@@ -185,6 +186,10 @@ def lib() -> ctypes.CDLL:
         L.lj_server_get_stats.argtypes = [vp, ctypes.POINTER(lj_server_stats)]
         L.lj_server_destroy.argtypes = [vp]
         L.lj_server_destroy.restype = None
+        L.lj_sort_join_workspace_bytes.argtypes = [u64, u64]
+        L.lj_sort_join_workspace_bytes.restype = u64
+        L.lj_sort_join_async.argtypes = [vp, u64, vp, u64, vp, u64, vp, vp, u64, vp]
+        L.lj_learned_sort_async.argtypes = [vp, u64, vp, vp, vp, u64, vp]
         L.lj_strerror.argtypes = [i32]
         L.lj_strerror.restype = ctypes.c_char_p
         for f in ("lj_build_rmi", "lj_build_rmi_host_only", "lj_probe_join",
@@ -194,7 +199,7 @@ def lib() -> ctypes.CDLL:
                   "lj_batch_plan_create", "lj_batch_plan_run", "lj_batch_autotune",
                   "lj_server_create", "lj_server_submit", "lj_server_submit_device",
                   "lj_server_wait",
-                  "lj_server_get_stats"):
+                  "lj_server_get_stats", "lj_sort_join_async", "lj_learned_sort_async"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -378,6 +383,40 @@ def lj_probe_join_async(index: Index, s_keys_dev, out_pairs_dev, count_dev, work
                                      _dev_ptr(out_pairs_dev) if cap else None, cap,
                                      _dev_ptr(count_dev), _dev_ptr(workspace_dev), ws_bytes,
                                      _stream_ptr(stream)), "lj_probe_join_async")
+
+
+def lj_sort_join_workspace_bytes(n: int, m: int) -> int:
+    return int(lib().lj_sort_join_workspace_bytes(n, m))
+
+
+def _nbytes(t) -> int:
+    return 0 if t is None else t.numel() * t.element_size()
+
+
+def lj_sort_join_async(r_keys_dev, s_keys_dev, out_pairs_dev, count_dev, workspace_dev,
+                       stream=None) -> None:
+    """Enqueue a learned sort join of two device key tensors in any order;
+    count_dev is a device int64 tensor of one element."""
+    n, m = r_keys_dev.numel(), s_keys_dev.numel()
+    cap = 0 if out_pairs_dev is None else out_pairs_dev.shape[0]
+    _check(lib().lj_sort_join_async(_dev_ptr(r_keys_dev) if n else None, n,
+                                    _dev_ptr(s_keys_dev) if m else None, m,
+                                    _dev_ptr(out_pairs_dev) if cap else None, cap,
+                                    _dev_ptr(count_dev), _dev_ptr(workspace_dev),
+                                    _nbytes(workspace_dev), _stream_ptr(stream)),
+           "lj_sort_join_async")
+
+
+def lj_learned_sort_async(keys_dev, sorted_keys_dev, positions_dev, workspace_dev,
+                          stream=None) -> None:
+    """Enqueue the learned sort of a device key tensor into (key, position)
+    order: sorted keys (int64/uint64 view) and int32 input positions."""
+    n = keys_dev.numel()
+    _check(lib().lj_learned_sort_async(_dev_ptr(keys_dev) if n else None, n,
+                                       _dev_ptr(sorted_keys_dev) if n else None,
+                                       _dev_ptr(positions_dev) if n else None,
+                                       _dev_ptr(workspace_dev), _nbytes(workspace_dev),
+                                       _stream_ptr(stream)), "lj_learned_sort_async")
 
 
 def lj_self_check(index: Index, stream=None) -> int:
@@ -565,3 +604,37 @@ def probe(index: Index, s_keys_dev, capacity: int | None = None, stream=None):
         st, cnt = lj_probe_join(index, s_keys_dev, out, stream)
         _check(st, "lj_probe_join")
     return out[:cnt]
+
+
+def sort_join(r_keys_dev, s_keys_dev, capacity: int | None = None, stream=None):
+    """Learned sort join of two device key tensors in any order; returns the
+    (count, 2) int32 CUDA tensor of (s_idx, r_idx) pairs and the true count.
+
+    With capacity None, a count-only join sizes the output first."""
+    import torch
+    dev = s_keys_dev.device
+    n, m = r_keys_dev.numel(), s_keys_dev.numel()
+    ws = torch.empty(max(lj_sort_join_workspace_bytes(n, m), 1), dtype=torch.uint8, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    if capacity is None:
+        lj_sort_join_async(r_keys_dev, s_keys_dev, None, cnt, ws, stream)
+        torch.cuda.synchronize(dev)
+        capacity = int(cnt.item())
+    out = torch.empty((max(capacity, 1), 2), dtype=torch.int32, device=dev)
+    lj_sort_join_async(r_keys_dev, s_keys_dev, out if capacity else None, cnt, ws, stream)
+    torch.cuda.synchronize(dev)
+    count = int(cnt.item())
+    return out[:min(count, capacity)], count
+
+
+def learned_sort(keys_dev, stream=None):
+    """(sorted keys as int64 bits, int32 input positions) of a device key tensor."""
+    import torch
+    dev = keys_dev.device
+    n = keys_dev.numel()
+    ws = torch.empty(max(lj_sort_join_workspace_bytes(n, 0), 1), dtype=torch.uint8, device=dev)
+    ko = torch.empty(n, dtype=torch.int64, device=dev)
+    po = torch.empty(n, dtype=torch.int32, device=dev)
+    lj_learned_sort_async(keys_dev, ko, po, ws, stream)
+    torch.cuda.synchronize(dev)
+    return ko, po

@@ -1,0 +1,152 @@
+"""GPU parity of the learned sort join (Section IV) and of its sort phase.
+
+Both relations come in any order.  The join's pairs are compared element by
+element with the oracle's sort join (``oracle.sort_join``: both relations
+sorted by (key, position) with qsort, merged, counting-sorted by s_idx);
+the learned sort's output with the oracle's (key, position) order
+(``oracle.sort_positions``).  Both are integer index work: the bar is exact
+equality.  Inputs are the named workloads with R shuffled (seeded), random
+relations with heavy duplication, and the edge cases of the method: one
+key, all keys equal, extreme keys, input already sorted or reversed, and a
+dense cluster that the model's sample misses (a partition too large for
+LDS, sorted by the global-memory fallback).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from paper_2111_08824_amd import lj
+
+pytestmark = pytest.mark.gpu
+
+U64MAX = 2**64 - 1
+
+
+def join_parity(R, S, label=""):
+    R = np.asarray(R, dtype=np.uint64)
+    S = np.asarray(S, dtype=np.uint64)
+    print(f"[sortjoin] {label} n={len(R)} m={len(S)}", flush=True)
+    got, count = lj.sort_join(lj.to_device_keys(R), lj.to_device_keys(S))
+    got = got.cpu().numpy().view(np.uint32).reshape(-1, 2)[:count]
+    want = oracle.sort_join(R, S)
+    assert count == len(want), (count, len(want))
+    assert np.array_equal(got, want)
+    return got
+
+
+def sort_parity(K, label=""):
+    K = np.asarray(K, dtype=np.uint64)
+    print(f"[learned-sort] {label} n={len(K)}", flush=True)
+    ko, po = lj.learned_sort(lj.to_device_keys(K))
+    wk, wp = oracle.sort_positions(K)
+    assert np.array_equal(ko.cpu().numpy().view(np.uint64), wk)
+    assert np.array_equal(po.cpu().numpy().view(np.uint32), wp)
+
+
+@pytest.mark.parametrize("make", [
+    lambda: workloads.c1_uniform(scale=0.3),
+    lambda: workloads.c2_lognormal_zipf(scale=0.002),
+    lambda: workloads.c3_dup_runs(scale=0.003),
+    lambda: workloads.c6_seq_holes(scale=0.002),
+], ids=["uniform", "lognormal-zipf", "dup-runs", "seq-holes"])
+def test_workloads_shuffled(make):
+    w = workloads.shuffled_inner(make())
+    join_parity(w.R, w.S, w.name)
+    sort_parity(w.R, w.name)
+    sort_parity(w.S, w.name + "-S")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_heavy_duplicates(seed):
+    rng = np.random.default_rng(100 + seed)
+    for n, m, dom in ((1, 1, 3), (7, 300, 5), (4097, 5000, 900), (70_000, 40_000, 20_000),
+                      (12_345, 99_999, 2**63)):
+        R = rng.integers(0, dom, n, dtype=np.uint64)
+        S = rng.integers(0, dom + 3, m, dtype=np.uint64)
+        join_parity(R, S, f"seed={seed} dom={dom}")
+        sort_parity(R, f"seed={seed} dom={dom}")
+
+
+def test_edge_cases():
+    R = np.array([U64MAX, 0, U64MAX, 1, 0, 2**63], dtype=np.uint64)
+    S = np.array([0, U64MAX, 2, 1, 2**63, U64MAX - 1], dtype=np.uint64)
+    join_parity(R, S, "extreme keys")
+    sort_parity(R, "extreme keys")
+    join_parity(np.full(20_000, 5, dtype=np.uint64), np.array([5, 4, 5], dtype=np.uint64),
+                "all equal")
+    sort_parity(np.full(20_000, 5, dtype=np.uint64), "all equal")
+    up = np.arange(100_000, dtype=np.uint64) * np.uint64(3)
+    join_parity(up, up[::7] + np.uint64(1), "sorted input")
+    join_parity(up[::-1].copy(), up[::5], "reversed input")
+    sort_parity(up[::-1].copy(), "reversed input")
+
+
+def test_cluster_missed_by_the_sample():
+    # n = 2 * 16384: the model samples the even positions only.  The odd
+    # positions hold 16384 distinct keys of one narrow range, in random
+    # order, between two sampled keys: one partition far larger than LDS.
+    rng = np.random.default_rng(3)
+    n = 2 * 16384
+    R = np.empty(n, dtype=np.uint64)
+    R[0::2] = rng.integers(0, 2**40, n // 2, dtype=np.uint64) * np.uint64(2**20)
+    R[1::2] = rng.permutation(np.arange(n // 2, dtype=np.uint64)) + np.uint64(2**50 + 1)
+    S = np.concatenate([R[::3], rng.integers(2**50, 2**50 + n, 5000, dtype=np.uint64)])
+    join_parity(R, S, "cluster")
+    sort_parity(R, "cluster")
+
+
+def test_capacity_and_count_only():
+    w = workloads.shuffled_inner(workloads.c3_dup_runs(scale=0.002))
+    R, S = lj.to_device_keys(w.R), lj.to_device_keys(w.S)
+    want = oracle.sort_join(w.R, w.S)
+    _, count = lj.sort_join(R, S, capacity=0)
+    assert count == len(want)
+    cap = len(want) // 3
+    got, count = lj.sort_join(R, S, capacity=cap)
+    assert count == len(want)
+    assert np.array_equal(got.cpu().numpy().view(np.uint32).reshape(-1, 2), want[:cap])
+
+
+def test_empty_relations():
+    import torch
+    e = torch.empty(0, dtype=torch.int64, device="cuda")
+    k = lj.to_device_keys(np.array([1, 2, 3], dtype=np.uint64))
+    assert lj.sort_join(e, k)[1] == 0
+    assert lj.sort_join(k, e)[1] == 0
+    ko, po = lj.learned_sort(e)
+    assert ko.numel() == 0 and po.numel() == 0
+
+
+def test_fullsize_sampled():
+    """lognormal-zipf-200M with R shuffled, the benchmark's launch: the
+    total equals the generator's exact hit count (R distinct, 90% hits), and
+    sampled pairs are checked one by one against the oracle's equal_range on
+    the sorted R mapped through the generator's shuffle."""
+    import torch
+    base = workloads.c2_lognormal_zipf()
+    w = workloads.shuffled_inner(base)
+    print(f"[sortjoin] full size n={len(w.R)} m={len(w.S)}", flush=True)
+    R, S = lj.to_device_keys(w.R), lj.to_device_keys(w.S)
+    n, m = len(w.R), len(w.S)
+    ws = torch.empty(lj.lj_sort_join_workspace_bytes(n, m), dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    cap = w.expected_count + 16
+    out = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
+    lj.lj_sort_join_async(R, S, out, cnt, ws)
+    torch.cuda.synchronize()
+    count = int(cnt.item())
+    assert count == w.expected_count
+    # Position of each sorted key in the shuffled R.
+    pos_of = np.empty(n, dtype=np.uint32)
+    order = np.argsort(w.R, kind="stable")
+    pos_of[:] = order.astype(np.uint32)  # pos_of[i] = shuffled position of base.R[i]
+    rng = np.random.default_rng(11)
+    idx = np.sort(rng.choice(count, 20_000, replace=False))
+    pairs = out[torch.from_numpy(idx).cuda()].cpu().numpy().view(np.uint32).reshape(-1, 2)
+    s_idx = pairs[:, 0].astype(np.int64)
+    first, c = oracle.equal_range(base.R, w.S[s_idx])
+    assert np.all(c == 1)
+    assert np.array_equal(pairs[:, 1], pos_of[first.astype(np.int64)])
+    # Pairs are in s order: the sampled s indices are non-decreasing.
+    assert np.all(np.diff(s_idx) >= 0)

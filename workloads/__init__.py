@@ -16,5 +16,6 @@ from .gen import (  # noqa: F401
 )
 from .configs import (  # noqa: F401
     Workload, c1_uniform, c2_lognormal_zipf, c3_dup_runs, c6_seq_holes, multi_index_batches,
+    shuffled_inner,
     default_leaves, resident_indexes,
 )

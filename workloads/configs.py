@@ -94,6 +94,14 @@ def c6_seq_holes(seed: int = 42, scale: float = 1.0) -> Workload:
                     {"n": n, "m": m, "hit_frac": 0.9, "dist": "seq_h (10% holes)"})
 
 
+def shuffled_inner(w: Workload, seed: int = 7) -> Workload:
+    """The same workload with R in a seeded random order: the unsorted inner
+    relation a sort-based join takes (Section IV).  S is unchanged."""
+    R = gen.shuffle(gen.stream_key(seed, 0x5a), w.R)
+    return Workload(w.name + "-shuffled", R, w.S, w.leaves, w.expected_count,
+                    dict(w.meta, r_order="shuffled"))
+
+
 def multi_index_batches(k: int = 64, seed: int = 42, n_lo: float = 1e4,
                         n_hi: float = 5e7, m_lo: float = 1e3, m_hi: float = 1e7):
     """k (R, S, leaves) triples: n log-uniform in [n_lo, n_hi], shape chosen
