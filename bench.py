@@ -116,6 +116,104 @@ def cpu_baseline(w, sample: int):
                       f"{len(w.R)} inner keys ({len(P)} pairs) in {dt:.2f} s, one thread"}
 
 
+def cpu_baseline_sort_join(w, sample: int):
+    import oracle
+    R, S = w.R[:sample], w.S[:sample]
+    t0 = time.perf_counter()
+    P = oracle.sort_join(R, S)
+    dt = time.perf_counter() - t0
+    return {"value": (len(R) + len(S)) / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
+            "sample": f"sort join (qsort of both sides, merge) of the first {len(R)} keys of "
+                      f"the shuffled R with the first {len(S)} keys of S ({len(P)} pairs) in "
+                      f"{dt:.2f} s, one thread"}
+
+
+def bench_sort_join(args) -> None:
+    """Learned sort join (Section IV) of the workload with R shuffled: one
+    step = one lj_sort_join_async of both whole relations (model, partition,
+    sort, join, emission) plus the count readback."""
+    import torch
+    import workloads
+    from paper_2111_08824_amd import lj
+
+    t0 = time.perf_counter()
+    w = workloads.shuffled_inner(make_workload(args.workload))
+    n, m = len(w.R), len(w.S)
+    print(f"[bench] workload {w.name}: n={n} m={m} ({time.perf_counter() - t0:.1f} s)",
+          file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    r_dev, s_dev = lj.to_device_keys(w.R), lj.to_device_keys(w.S)
+    ws = torch.empty(lj.lj_sort_join_workspace_bytes(n, m), dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    cnt_host = torch.zeros(1, dtype=torch.int64, pin_memory=True)
+    cap = w.expected_count if w.expected_count is not None else 0
+    if not cap:
+        lj.lj_sort_join_async(r_dev, s_dev, None, cnt, ws, stream)
+        cap = int(cnt.item())
+    out = torch.empty((max(cap, 1), 2), dtype=torch.int32, device="cuda")
+
+    def step():
+        lj.lj_sort_join_async(r_dev, s_dev, out, cnt, ws, stream)
+        cnt_host.copy_(cnt, non_blocking=True)
+        stream.synchronize()
+        return int(cnt_host.item())
+
+    for _ in range(args.warmup):
+        count = step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    for a, b in ev:
+        a.record(stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    lat = []
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        lj.lj_probe_set_timing_events(ev[i][0], ev[i][1])
+        a = time.perf_counter()
+        count = step()
+        lat.append(time.perf_counter() - a)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    if w.expected_count is not None and count != w.expected_count:
+        raise SystemExit(f"pair count {count} != expected {w.expected_count}")
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    ms_per_step = wall * 1e3 / args.steps
+    # Join kernel: per key of S its key (8 B) and partition number (4 B)
+    # read, one 64 B sector of the sorted R searched, an 8 B result written.
+    alg = 84.0 * m
+    achieved = alg / (kern_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes_per_launch": alg, "kernel": "sj_join_kernel",
+            "kernel_ms": round(kern_ms, 4)}
+    cpu = (cpu_baseline_sort_join(w, min(args.cpu_sample // 4, n, m)) if args.cpu_sample
+           else None)
+    lat_ms = np.array(lat) * 1e3
+    res = {
+        "metric": "join tuples/sec ((|R| + |S|) per second), learned sort join",
+        "value": (n + m) / (ms_per_step * 1e-3),
+        "unit": "tuples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": n, "m": m, "join": "learned-sort",
+                   "pairs": int(count)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
+                       "p99": round(float(np.percentile(lat_ms, 99)), 4)},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def _json_line(res: dict) -> None:
     print(json.dumps(res), flush=True)
 
@@ -354,6 +452,9 @@ def main():
                          "learned hash (the RMI as hash function of a bucket-chained table)")
     ap.add_argument("--slots-per-key", type=int, default=4,
                     help="gapped RMI or learned hash: slots per key of R")
+    ap.add_argument("--join", choices=["inlj", "lsj"], default="inlj",
+                    help="learned indexed nested loop join (index on sorted R), or the "
+                         "learned sort join of R shuffled and S")
     ap.add_argument("--cpu-sample", type=int, default=120_000_000,
                     help="outer keys in the timed oracle sample (0 = skip)")
     ap.add_argument("--requests", type=int, default=1000,
@@ -375,6 +476,8 @@ def main():
         return bench_multi_index(args)
     if args.workload == "serving-8x50M":
         return bench_serving(args)
+    if args.join == "lsj":
+        return bench_sort_join(args)
 
     import torch
     from paper_2111_08824_amd import lj

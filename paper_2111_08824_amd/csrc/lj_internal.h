@@ -339,7 +339,7 @@ inline SortJoinWs sort_join_ws(uint64_t n, uint64_t m) {
     }
     L.counts = a;  // pairs per chunk of S, then their exclusive prefix (+ total)
     a = align_up256(a + (nchs + 1) * 8);
-    L.big_queue = a;  // count, then the partitions too large for LDS
+    L.big_queue = a;  // count, the partitions too large for LDS, the join's run flag
     a = align_up256(a + 8 + (uint64_t)L.parts * 4);
     L.ctrl_bytes = a;
     L.knots = a;

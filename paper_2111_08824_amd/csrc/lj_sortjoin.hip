@@ -84,36 +84,24 @@ __global__ __launch_bounds__(kModelThreads) void sj_model_kernel(
     }
 }
 
-// Partition number of key x: below the first knot and from the last knot on
-// by key bucket distance, inside segment [k0, k1) by linear interpolation.
-// Non-decreasing in x.
-__device__ inline uint32_t sj_pid(uint64_t x, const uint64_t* kn, const uint16_t* kl,
-                                  uint32_t nk, uint32_t fan) {
-    const uint32_t bk = key_bucket(x);
-    uint32_t b = kl[bk], len = kl[bk + 1] - kl[bk];
-    while (len) {
-        const uint32_t half = len >> 1, at = b + half;
-        if (kn[at] <= x) {
-            b = at + 1;
-            len -= half + 1;
-        } else {
-            len = half;
-        }
-    }
-    // b = number of knots <= x.
-    if (b == 0) {
-        const uint32_t d = key_bucket(kn[0]) - bk;
-        return fan - 1 - (d < fan - 1 ? d : fan - 1);
-    }
+// Sub-partition of fraction f >= 0 of a segment among fan (f >= 1: the last).
+__device__ inline uint32_t sj_sub(double f, uint32_t fan) {
+    return f < 1.0 ? min((uint32_t)(f * (double)fan), fan - 1) : fan - 1;
+}
+
+// Partition number of key x by linear interpolation: inside segment
+// [k0, k1), below the first knot over [0, k0), from the last knot k on over
+// [k, 2k) (keys beyond in the last one).  Non-decreasing in x.
+// b = number of knots <= x.
+__device__ inline uint32_t sj_pid_of(uint64_t x, uint32_t b, const uint64_t* kn, uint32_t nk,
+                                     uint32_t fan) {
+    if (b == 0) return sj_sub((double)x / (double)kn[0], fan);
     if (b > nk) {
-        const uint32_t d = bk - key_bucket(kn[nk]);
-        return (nk + 1) * fan + (d < fan - 1 ? d : fan - 1);
+        const uint64_t k = kn[nk];
+        return (nk + 1) * fan + sj_sub((double)(x - k) / (double)(k ? k : 1), fan);
     }
     const uint64_t k0 = kn[b - 1], k1 = kn[b];
-    const double frac = (double)(x - k0) / (double)(k1 - k0);
-    uint32_t sub = (uint32_t)(frac * (double)fan);
-    sub = sub < fan ? sub : fan - 1;
-    return b * fan + sub;
+    return b * fan + sj_sub((double)(x - k0) / (double)(k1 - k0), fan);
 }
 
 // Per chunk of kPartChunk keys: histogram of the pid digit at `shift`
@@ -137,20 +125,53 @@ __global__ __launch_bounds__(kBlock) void sj_hist_kernel(
         if (tid < (int)kDigits) cnt[tid] = 0;
         __syncthreads();
         const uint64_t e0 = (uint64_t)c * kPartChunk + (uint64_t)wave * kWaveSpan + lane;
+        uint32_t pid[kPartItems];
+        if constexpr (kFromKeys) {
+            // Knots <= x: those of lower key buckets plus a lockstep binary
+            // search over the knots of x's own bucket.
+            uint64_t x[kPartItems];
+            uint32_t b[kPartItems], len[kPartItems];
 #pragma unroll
-        for (int k = 0; k < (int)kPartItems; ++k) {
-            const uint64_t p = e0 + (uint64_t)k * 64;
-            if (p < m) {
-                uint32_t pid;
-                if constexpr (kFromKeys) {
-                    pid = sj_pid(keys[p], sk, sl, nk, fan);
-                    pids[p] = pid;
-                } else {
-                    pid = pids[p];
+            for (int k = 0; k < (int)kPartItems; ++k) {
+                const uint64_t p = e0 + (uint64_t)k * 64;
+                x[k] = keys[p < m ? p : m - 1];
+            }
+#pragma unroll
+            for (int k = 0; k < (int)kPartItems; ++k) {
+                const uint32_t bk = key_bucket(x[k]);
+                b[k] = sl[bk];
+                len[k] = sl[bk + 1] - b[k];
+            }
+            for (;;) {
+                uint32_t act = 0;
+#pragma unroll
+                for (int k = 0; k < (int)kPartItems; ++k) act |= len[k];
+                if (!act) break;
+#pragma unroll
+                for (int k = 0; k < (int)kPartItems; ++k) {
+                    const uint32_t half = len[k] >> 1;
+                    const uint32_t at = b[k] + half;
+                    const bool le = len[k] != 0 && sk[at <= nk ? at : nk] <= x[k];
+                    b[k] = le ? at + 1 : b[k];
+                    len[k] = le ? len[k] - half - 1 : half;
                 }
-                atomicAdd(&cnt[sj_digit(pid, shift)], 1u);
+            }
+#pragma unroll
+            for (int k = 0; k < (int)kPartItems; ++k) {
+                pid[k] = sj_pid_of(x[k], b[k], sk, nk, fan);
+                const uint64_t p = e0 + (uint64_t)k * 64;
+                if (p < m) pids[p] = pid[k];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < (int)kPartItems; ++k) {
+                const uint64_t p = e0 + (uint64_t)k * 64;
+                pid[k] = p < m ? pids[p] : 0u;
             }
         }
+#pragma unroll
+        for (int k = 0; k < (int)kPartItems; ++k)
+            if (e0 + (uint64_t)k * 64 < m) atomicAdd(&cnt[sj_digit(pid[k], shift)], 1u);
         __syncthreads();
         if (tid < (int)kDigits) hist[(uint64_t)tid * nchunks + c] = cnt[tid];
         __syncthreads();
@@ -334,12 +355,16 @@ __global__ __launch_bounds__(kBlock) void sj_sort_kernel(uint64_t* __restrict__ 
     }
 }
 
-// Partitions larger than LDS: one block each, in global memory; a
-// partition already in (key, position) order (e.g. one repeated key, kept
-// in input order by the stable passes) is left as is.
+// Partitions larger than kSjSortCap: one block of kBigThreads each, in LDS
+// up to kBigCap keys, else in global memory; a partition already in (key,
+// position) order (e.g. one repeated key, kept in input order by the stable
+// passes) is left as is.
+constexpr uint32_t kBigCap = 10240;
 __global__ __launch_bounds__(kBigThreads) void sj_sort_big_kernel(
     uint64_t* __restrict__ keys, uint32_t* __restrict__ pos,
     const uint32_t* __restrict__ start, const uint32_t* __restrict__ big) {
+    __shared__ uint64_t sk[kBigCap];
+    __shared__ uint32_t sp[kBigCap];
     __shared__ int unsorted;
     const uint32_t tid = threadIdx.x;
     const uint32_t nbig = big[0];
@@ -355,19 +380,38 @@ __global__ __launch_bounds__(kBigThreads) void sj_sort_big_kernel(
         __syncthreads();
         const bool work = unsorted != 0;
         __syncthreads();
-        if (work) sj_bitonic(keys + a, pos + a, sz, tid, kBigThreads);
+        if (work && sz <= kBigCap) {
+            for (uint32_t i = tid; i < sz; i += kBigThreads) {
+                sk[i] = keys[a + i];
+                sp[i] = pos[a + i];
+            }
+            __syncthreads();
+            sj_bitonic(sk, sp, sz, tid, kBigThreads);
+            for (uint32_t i = tid; i < sz; i += kBigThreads) {
+                keys[a + i] = sk[i];
+                pos[a + i] = sp[i];
+            }
+        } else if (work) {
+            sj_bitonic(keys + a, pos + a, sz, tid, kBigThreads);
+        }
         __syncthreads();
     }
 }
 
 // Join: S in coarse pid order, each key's run found by lower and upper
-// bound inside its own partition of the sorted R; res[q] = first position
-// | run length << 32, in the same order as the keys.  Blocks are mapped
-// XCD-contiguously so that one XCD's L2 serves neighbouring partitions.
+// bound inside its own partition of the sorted R; res[q] = v | run length
+// << 32 in the same order as the keys, where v is the input position in R
+// of a single match (read here, where that part of R is in cache), or
+// kSortedPos | the first sorted position of a longer run (then *runs is
+// set, and the emitted positions are mapped afterwards).  Blocks are
+// mapped XCD-contiguously so that one XCD's L2 serves neighbouring
+// partitions.
+constexpr uint32_t kSortedPos = 0x80000000u;
 __global__ __launch_bounds__(kBlock) void sj_join_kernel(
     const uint64_t* __restrict__ sk, const uint32_t* __restrict__ spid, uint64_t m,
-    const uint64_t* __restrict__ rk, const uint32_t* __restrict__ rstart, uint32_t ntiles,
-    uint32_t tiles_per_xcd, uint64_t* __restrict__ res) {
+    const uint64_t* __restrict__ rk, const uint32_t* __restrict__ rpos,
+    const uint32_t* __restrict__ rstart, uint32_t ntiles, uint32_t tiles_per_xcd,
+    uint64_t* __restrict__ res, uint32_t* __restrict__ runs) {
     const uint32_t tile = (blockIdx.x % kXcds) * tiles_per_xcd + blockIdx.x / kXcds;
     if (tile >= ntiles) return;
     const uint64_t base = (uint64_t)tile * kBlock * kJoinItems + threadIdx.x;
@@ -432,23 +476,32 @@ __global__ __launch_bounds__(kBlock) void sj_join_kernel(
             }
         }
     }
+    bool longer = false;
 #pragma unroll
     for (int k = 0; k < kJoinItems; ++k) {
         const uint64_t q = base + (uint64_t)k * kBlock;
-        if (q < m) res[q] = (uint64_t)b[k] | ((uint64_t)(e[k] - b[k]) << 32);
+        const uint32_t c = e[k] - b[k];
+        uint32_t v = b[k] | kSortedPos;
+        if (c == 1) v = rpos[b[k]];
+        longer |= q < m && c > 1;
+        if (q < m) res[q] = (uint64_t)v | ((uint64_t)c << 32);
     }
+    if (__ballot(longer) && (threadIdx.x & 63) == 0) atomicOr(runs, 1u);
 }
 
-// Emitted r indices are positions in the sorted R: map them to R's input
-// positions (the written pairs only: min(total, cap)).
+// Pairs of runs longer than one were emitted with kSortedPos | sorted
+// position: map those to R's input positions (written pairs only:
+// min(total, cap)); nothing to do unless the join saw such a run.
 __global__ void sj_map_kernel(lj_pair* __restrict__ out, uint64_t cap,
                               const uint64_t* __restrict__ count,
+                              const uint32_t* __restrict__ runs,
                               const uint32_t* __restrict__ rpos, uint64_t n) {
+    if (*runs == 0) return;
     const uint64_t c = *count, lim = c < cap ? c : cap;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < lim;
          i += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t r = out[i].r_idx;
-        if (r < n) out[i].r_idx = rpos[r];
+        if ((r & kSortedPos) && (r & ~kSortedPos) < n) out[i].r_idx = rpos[r & ~kSortedPos];
     }
 }
 
@@ -594,8 +647,10 @@ hipError_t launch_sort_join(const uint64_t* r, uint64_t n, const uint64_t* s, ui
     }
     const uint32_t ntiles = (uint32_t)num_tiles(m, (uint64_t)kBlock * kJoinItems);
     const uint32_t tpx = (uint32_t)num_tiles(ntiles, kXcds);
+    uint32_t* runs = (uint32_t*)(w + L.big_queue) + 1 + L.parts;
     hipLaunchKernelGGL(sj_join_kernel, dim3(tpx * kXcds), dim3(kBlock), 0, stream, sk, spid, m,
-                       (const uint64_t*)rk, (const uint32_t*)(w + L.r_start), ntiles, tpx, res2);
+                       (const uint64_t*)rk, (const uint32_t*)rp,
+                       (const uint32_t*)(w + L.r_start), ntiles, tpx, res2, runs);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev1) {
@@ -618,7 +673,8 @@ hipError_t launch_sort_join(const uint64_t* r, uint64_t n, const uint64_t* s, ui
     if (e != hipSuccess) return e;
     if (out && cap)
         hipLaunchKernelGGL(sj_map_kernel, dim3(4096), dim3(kBlock), 0, stream, out, cap,
-                           (const uint64_t*)count_dev, (const uint32_t*)rp, n);
+                           (const uint64_t*)count_dev, (const uint32_t*)runs,
+                           (const uint32_t*)rp, n);
     return hipGetLastError();
 }
 

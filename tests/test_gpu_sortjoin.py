@@ -7,9 +7,10 @@ the learned sort's output with the oracle's (key, position) order
 (``oracle.sort_positions``).  Both are integer index work: the bar is exact
 equality.  Inputs are the named workloads with R shuffled (seeded), random
 relations with heavy duplication, and the edge cases of the method: one
-key, all keys equal, extreme keys, input already sorted or reversed, and a
-dense cluster that the model's sample misses (a partition too large for
-LDS, sorted by the global-memory fallback).
+key, all keys equal, extreme keys, input already sorted or reversed, and
+dense clusters that the model's sample misses (partitions beyond the
+per-partition LDS sort, taken by the larger-block LDS sort and by the
+global-memory sort).
 """
 import numpy as np
 import pytest
@@ -82,18 +83,20 @@ def test_edge_cases():
     sort_parity(up[::-1].copy(), "reversed input")
 
 
-def test_cluster_missed_by_the_sample():
-    # n = 2 * 16384: the model samples the even positions only.  The odd
-    # positions hold 16384 distinct keys of one narrow range, in random
-    # order, between two sampled keys: one partition far larger than LDS.
+@pytest.mark.parametrize("cluster", [6000, 16384])
+def test_cluster_missed_by_the_sample(cluster):
+    # n = 2 * 16384: the model samples the even positions only.  `cluster`
+    # odd positions hold distinct keys of one narrow range, in random order,
+    # between two sampled keys: one partition larger than the LDS sort takes
+    # (6000: sorted in LDS by a larger block; 16384: in global memory).
     rng = np.random.default_rng(3)
     n = 2 * 16384
-    R = np.empty(n, dtype=np.uint64)
-    R[0::2] = rng.integers(0, 2**40, n // 2, dtype=np.uint64) * np.uint64(2**20)
-    R[1::2] = rng.permutation(np.arange(n // 2, dtype=np.uint64)) + np.uint64(2**50 + 1)
+    R = rng.integers(0, 2**40, n, dtype=np.uint64) * np.uint64(2**20)
+    odd = np.arange(1, n, 2)[:cluster]
+    R[odd] = rng.permutation(np.arange(cluster, dtype=np.uint64)) + np.uint64(2**50 + 1)
     S = np.concatenate([R[::3], rng.integers(2**50, 2**50 + n, 5000, dtype=np.uint64)])
-    join_parity(R, S, "cluster")
-    sort_parity(R, "cluster")
+    join_parity(R, S, f"cluster {cluster}")
+    sort_parity(R, f"cluster {cluster}")
 
 
 def test_capacity_and_count_only():
