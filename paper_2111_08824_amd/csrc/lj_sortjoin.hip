@@ -324,8 +324,142 @@ __device__ void sj_bitonic(K* key, P* pos, uint32_t sz, uint32_t tid, uint32_t n
     }
 }
 
-// Sort every partition of at most kSjSortCap keys in LDS; queue the larger
-// ones for sj_sort_big_kernel.
+// Wave sort of up to 64 * E (key, position) elements in registers: lane L
+// holds elements L * E .. L * E + E - 1, padded past sz with (~0, ~0), which
+// orders after every real element (positions are below 2^31).  The same
+// all-ascending bitonic network as sj_bitonic: comparators closer than E
+// elements are register exchanges, the others a cross-lane shuffle (the
+// lower element of each pair keeps the minimum, the upper the maximum).
+__device__ inline bool sj_less(uint64_t ka, uint32_t pa, uint64_t kb, uint32_t pb) {
+    return ka < kb || (ka == kb && pa < pb);
+}
+
+template <int E>
+__device__ void sj_sort_wave(uint64_t* __restrict__ keys, uint32_t* __restrict__ pos,
+                             uint32_t sz, uint32_t lane) {
+    uint64_t k[E];
+    uint32_t p[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const uint32_t e = lane * E + r;
+        k[r] = e < sz ? keys[e] : ~0ull;
+        p[r] = e < sz ? pos[e] : ~0u;
+    }
+    // Register comparator (i, j), i < j: ascending.
+    auto cx = [&](int i, int j) {
+        if (sj_less(k[j], p[j], k[i], p[i])) {
+            const uint64_t tk = k[i];
+            const uint32_t tp = p[i];
+            k[i] = k[j];
+            p[i] = p[j];
+            k[j] = tk;
+            p[j] = tp;
+        }
+    };
+    // Element r against the partner lane's element (the lower lane keeps the
+    // minimum).
+    auto keep = [&](int r, uint64_t ok, uint32_t op, bool lower) {
+        const bool take = lower ? sj_less(ok, op, k[r], p[r]) : sj_less(k[r], p[r], ok, op);
+        k[r] = take ? ok : k[r];
+        p[r] = take ? op : p[r];
+    };
+    // Register half-cleaners at distances E/2 .. 1.
+    auto local_cleaners = [&]() {
+#pragma unroll
+        for (int d = E / 2; d > 0; d >>= 1) {
+#pragma unroll
+            for (int r = 0; r < E; ++r)
+                if ((r & d) == 0) cx(r, r | d);
+        }
+    };
+    // Stages up to E: inside each lane.
+#pragma unroll
+    for (int st = 2; st <= E; st <<= 1) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int r2 = r ^ (st - 1);
+            if (r < r2) cx(r, r2);
+        }
+#pragma unroll
+        for (int d = st >> 2; d > 0; d >>= 1) {
+#pragma unroll
+            for (int r = 0; r < E; ++r)
+                if ((r & d) == 0) cx(r, r | d);
+        }
+    }
+    // Stages beyond E: the mirror step and the half-cleaners down to E
+    // across lanes, then the rest in registers.
+    constexpr uint32_t N = 64u * E;
+#pragma unroll 1
+    for (uint32_t st = 2 * E; st <= N; st <<= 1) {
+        {
+            const int src = (int)(lane ^ (st / E - 1));
+            const bool lower = (lane & (st / (2 * E))) == 0;
+#pragma unroll
+            for (int r = 0; r < E / 2; ++r) {
+                const int r2 = E - 1 - r;
+                const uint64_t ka = __shfl(k[r2], src, 64), kb = __shfl(k[r], src, 64);
+                const uint32_t pa = __shfl(p[r2], src, 64), pb = __shfl(p[r], src, 64);
+                keep(r, ka, pa, lower);
+                keep(r2, kb, pb, lower);
+            }
+            if constexpr (E == 1) {
+                const uint64_t ka = __shfl(k[0], src, 64);
+                const uint32_t pa = __shfl(p[0], src, 64);
+                keep(0, ka, pa, lower);
+            }
+        }
+#pragma unroll 1
+        for (uint32_t d = st >> 2; d >= (uint32_t)E; d >>= 1) {
+            const int src = (int)(lane ^ (d / E));
+            const bool lower = (lane & (d / E)) == 0;
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const uint64_t ok = __shfl(k[r], src, 64);
+                const uint32_t op = __shfl(p[r], src, 64);
+                keep(r, ok, op, lower);
+            }
+        }
+        local_cleaners();
+    }
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const uint32_t e = lane * E + r;
+        if (e < sz) {
+            keys[e] = k[r];
+            pos[e] = p[r];
+        }
+    }
+}
+
+// One wave per partition of kLo + 1 .. kHi keys (kHi <= 1024, or the
+// 2048-key sort alone: its 32 elements per lane need about twice the
+// registers, which would halve the occupancy of the smaller sorts).
+constexpr uint32_t kSjWaveCap = 2048;
+template <uint32_t kLo, uint32_t kHi>
+__global__ __launch_bounds__(kBlock) void sj_sort_wave_kernel(uint64_t* __restrict__ keys,
+                                                              uint32_t* __restrict__ pos,
+                                                              const uint32_t* __restrict__ start,
+                                                              uint32_t parts) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t waves = gridDim.x * (kBlock / 64);
+    for (uint32_t p = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); p < parts; p += waves) {
+        const uint32_t a = start[p], sz = start[p + 1] - a;
+        if (sz <= kLo || sz > kHi || sz <= 1) continue;
+        if constexpr (kHi > 1024) {
+            sj_sort_wave<32>(keys + a, pos + a, sz, lane);
+        } else {
+            if (sz <= 64) sj_sort_wave<1>(keys + a, pos + a, sz, lane);
+            else if (sz <= 128) sj_sort_wave<2>(keys + a, pos + a, sz, lane);
+            else if (sz <= 256) sj_sort_wave<4>(keys + a, pos + a, sz, lane);
+            else if (sz <= 512) sj_sort_wave<8>(keys + a, pos + a, sz, lane);
+            else sj_sort_wave<16>(keys + a, pos + a, sz, lane);
+        }
+    }
+}
+
+// Sort every partition of kSjWaveCap + 1 .. kSjSortCap keys in LDS; queue
+// the larger ones for sj_sort_big_kernel.
 __global__ __launch_bounds__(kBlock) void sj_sort_kernel(uint64_t* __restrict__ keys,
                                                          uint32_t* __restrict__ pos,
                                                          const uint32_t* __restrict__ start,
@@ -336,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void sj_sort_kernel(uint64_t* __restrict__ 
     const uint32_t tid = threadIdx.x;
     for (uint32_t p = blockIdx.x; p < parts; p += gridDim.x) {
         const uint32_t a = start[p], sz = start[p + 1] - a;
-        if (sz <= 1) continue;
+        if (sz <= kSjWaveCap) continue;
         if (sz > kSjSortCap) {
             if (tid == 0) big[1 + atomicAdd(&big[0], 1u)] = p;
             continue;
@@ -589,6 +723,11 @@ hipError_t learned_sort(const uint64_t* keys, uint64_t n, uint64_t* keys_out, ui
     hipLaunchKernelGGL(sj_bounds_kernel, dim3(grid_of(num_tiles(n + 1, kBlock), 8192)),
                        dim3(kBlock), 0, stream, pids, n, L.parts, start);
     uint32_t* big = (uint32_t*)(w + L.big_queue);
+    const dim3 wgrid(grid_of(num_tiles(L.parts, kBlock / 64), 16384));
+    hipLaunchKernelGGL((sj_sort_wave_kernel<0, 1024>), wgrid, dim3(kBlock), 0, stream, keys_out,
+                       pos_out, (const uint32_t*)start, L.parts);
+    hipLaunchKernelGGL((sj_sort_wave_kernel<1024, kSjWaveCap>), wgrid, dim3(kBlock), 0, stream,
+                       keys_out, pos_out, (const uint32_t*)start, L.parts);
     hipLaunchKernelGGL(sj_sort_kernel, dim3(grid_of(L.parts, 16384)), dim3(kBlock), 0, stream,
                        keys_out, pos_out, (const uint32_t*)start, L.parts, big);
     hipLaunchKernelGGL(sj_sort_big_kernel, dim3(256), dim3(kBigThreads), 0, stream, keys_out,

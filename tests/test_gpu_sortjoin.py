@@ -69,6 +69,19 @@ def test_random_heavy_duplicates(seed):
         sort_parity(R, f"seed={seed} dom={dom}")
 
 
+@pytest.mark.parametrize("n", [2**18, 2**20, 2**22])
+def test_partition_sizes_span_every_sort_path(n):
+    # Mean partition sizes of about 64, 256 and 1024 keys: the partitions
+    # spread over every wave sort width (64 .. 2048 keys) and, at 2^22, the
+    # block sort beyond 2048 keys.
+    rng = np.random.default_rng(n)
+    R = rng.integers(0, 2**62, n, dtype=np.uint64)
+    S = np.concatenate([R[rng.integers(0, n, n // 4)],
+                        rng.integers(0, 2**62, n // 4, dtype=np.uint64)])
+    join_parity(R, S, f"uniform n={n}")
+    sort_parity(R, f"uniform n={n}")
+
+
 def test_edge_cases():
     R = np.array([U64MAX, 0, U64MAX, 1, 0, 2**63], dtype=np.uint64)
     S = np.array([0, U64MAX, 2, 1, 2**63, U64MAX - 1], dtype=np.uint64)
