@@ -310,7 +310,7 @@ constexpr uint32_t kSjMaxPasses = 4;
 struct SortJoinWs {
     uint32_t ns, nk, fan, parts, nbits, rpasses, spasses, s_shift;
     uint64_t scan_ctr, scan_st[kSjMaxPasses + 3], counts, big_queue, ctrl_bytes;
-    uint64_t knots, kb_lo, r_hist, r_bins[2], r_keys[2], r_pos[2], r_start;
+    uint64_t knots, kb_lo, r_hist, r_bins[2], r_keys[2], r_pos[2], r_start, r_rs;
     uint64_t s_hist, s_bins[2], s_keys[2], s_dest[2], total;
 };
 inline SortJoinWs sort_join_ws(uint64_t n, uint64_t m) {
@@ -358,6 +358,8 @@ inline SortJoinWs sort_join_ws(uint64_t n, uint64_t m) {
     }
     L.r_start = a;
     a = align_up256(a + ((uint64_t)L.parts + 1) * 4);
+    L.r_rs = a;  // line samples of the sorted R
+    a = align_up256(a + num_tiles(n, kLineKeys) * 8);
     L.s_hist = a;
     a = align_up256(a + nhs * 4);
     for (int k = 0; k < 2; ++k) {

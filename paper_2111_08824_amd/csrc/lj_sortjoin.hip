@@ -543,7 +543,8 @@ __global__ __launch_bounds__(kBigThreads) void sj_sort_big_kernel(
 constexpr uint32_t kSortedPos = 0x80000000u;
 __global__ __launch_bounds__(kBlock) void sj_join_kernel(
     const uint64_t* __restrict__ sk, const uint32_t* __restrict__ spid, uint64_t m,
-    const uint64_t* __restrict__ rk, const uint32_t* __restrict__ rpos,
+    const uint64_t* __restrict__ rk, const uint64_t* __restrict__ rs,
+    const uint32_t* __restrict__ rpos,
     const uint32_t* __restrict__ rstart, uint32_t ntiles, uint32_t tiles_per_xcd,
     uint64_t* __restrict__ res, uint32_t* __restrict__ runs) {
     const uint32_t tile = (blockIdx.x % kXcds) * tiles_per_xcd + blockIdx.x / kXcds;
@@ -561,7 +562,45 @@ __global__ __launch_bounds__(kBlock) void sj_join_kernel(
         hi[k] = v ? rstart[p + 1] : 0;
         len[k] = hi[k] - b[k];
     }
-    // Lower bound in lockstep.
+    // Lower bound in two lockstep stages: over the line samples
+    // rs[j] = rk[kLineKeys * j] that fall in the partition, then inside the
+    // one line that holds the bound.
+    uint32_t lim[kJoinItems];
+#pragma unroll
+    for (int k = 0; k < kJoinItems; ++k) {
+        const uint32_t j0 = (b[k] + kLineKeys - 1) / kLineKeys;
+        lim[k] = j0;  // first sample of the partition
+        len[k] = (hi[k] + kLineKeys - 1) / kLineKeys - j0;
+    }
+    uint32_t c[kJoinItems];
+#pragma unroll
+    for (int k = 0; k < kJoinItems; ++k) c[k] = lim[k];
+    for (;;) {
+        uint32_t act = 0;
+#pragma unroll
+        for (int k = 0; k < kJoinItems; ++k) act |= len[k];
+        if (!act) break;
+#pragma unroll
+        for (int k = 0; k < kJoinItems; ++k) {
+            if (len[k]) {
+                const uint32_t half = len[k] >> 1, at = c[k] + half;
+                if (rs[at] < x[k]) {
+                    c[k] = at + 1;
+                    len[k] -= half + 1;
+                } else {
+                    len[k] = half;
+                }
+            }
+        }
+    }
+    // rk[kLineKeys * (c - 1)] < x <= rk[kLineKeys * c] (where those are in
+    // the partition): the bound is in [kLineKeys * (c - 1) + 1, kLineKeys * c].
+#pragma unroll
+    for (int k = 0; k < kJoinItems; ++k) {
+        const uint32_t end = min(hi[k], c[k] * kLineKeys);
+        b[k] = c[k] > lim[k] ? (c[k] - 1) * kLineKeys + 1 : b[k];
+        len[k] = end - b[k];
+    }
     for (;;) {
         uint32_t act = 0;
 #pragma unroll
@@ -787,8 +826,11 @@ hipError_t launch_sort_join(const uint64_t* r, uint64_t n, const uint64_t* s, ui
     const uint32_t ntiles = (uint32_t)num_tiles(m, (uint64_t)kBlock * kJoinItems);
     const uint32_t tpx = (uint32_t)num_tiles(ntiles, kXcds);
     uint32_t* runs = (uint32_t*)(w + L.big_queue) + 1 + L.parts;
+    uint64_t* rs = (uint64_t*)(w + L.r_rs);
+    e = launch_line_samples(rk, n, rs, stream);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sj_join_kernel, dim3(tpx * kXcds), dim3(kBlock), 0, stream, sk, spid, m,
-                       (const uint64_t*)rk, (const uint32_t*)rp,
+                       (const uint64_t*)rk, (const uint64_t*)rs, (const uint32_t*)rp,
                        (const uint32_t*)(w + L.r_start), ntiles, tpx, res2, runs);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
