@@ -45,6 +45,43 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+SORT_JOIN_SOURCES = ["paper_2111_08824_amd/csrc/lj_sortjoin.hip",
+                     "paper_2111_08824_amd/csrc/lj_sortjoin.h",
+                     "paper_2111_08824_amd/csrc/lj_device.h",
+                     "paper_2111_08824_amd/csrc/lj_internal.h"]
+
+
+def kernel_source_hash_sort_join() -> str:
+    h = hashlib.sha256()
+    for f in SORT_JOIN_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _counter_summary(path: str, sha: str):
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != sha:
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def load_traffic_sort_join(workload: str):
+    """HBM bytes per launch of the sort join's join kernel from the committed
+    counter summary, or None when absent or taken on other kernel sources."""
+    return _counter_summary(os.path.join(ROOT, "profiles", f"sort_join_{workload}_hbm_counters.md"),
+                            kernel_source_hash_sort_join())
+
+
 def load_traffic(workload: str, binned: bool, index: str = "rmi"):
     """HBM bytes per launch of the timed kernel from the committed rocprofv3
     counter summary, or None when absent or taken on a different kernel
@@ -180,12 +217,20 @@ def bench_sort_join(args) -> None:
         raise SystemExit(f"pair count {count} != expected {w.expected_count}")
     kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     ms_per_step = wall * 1e3 / args.steps
+    if args.copy_calibration_mib:
+        src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     # Join kernel: per key of S its key (8 B) and partition number (4 B)
     # read, one 64 B sector of the sorted R searched, an 8 B result written.
     alg = 84.0 * m
     achieved = alg / (kern_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": load_traffic_sort_join(w.name),
             "algorithmic_bytes_per_launch": alg, "kernel": "sj_join_kernel",
             "kernel_ms": round(kern_ms, 4)}
     cpu = (cpu_baseline_sort_join(w, min(args.cpu_sample // 4, n, m)) if args.cpu_sample

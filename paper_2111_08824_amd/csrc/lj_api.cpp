@@ -9,6 +9,7 @@
 #include <unordered_map>
 
 #include "lj_internal.h"
+#include "lj_sortjoin.h"
 
 namespace {
 

@@ -23,7 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include "lj_device.h"
-#include "lj_internal.h"
+#include "lj_sortjoin.h"
 
 namespace lj {
 namespace {
