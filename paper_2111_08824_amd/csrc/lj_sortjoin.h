@@ -19,10 +19,10 @@ namespace lj {
 // global memory).  S is put in coarse pid order by two passes and each key
 // is found in its own partition of the sorted R.
 constexpr uint32_t kSjSamples = 16384;
-constexpr uint32_t kSjSamplesPerKnot = 4;
+constexpr uint32_t kSjSamplesPerKnot = 16;
 constexpr uint32_t kSjMaxSegments = kSjSamples / kSjSamplesPerKnot - 2;
 constexpr uint32_t kSjTargetPart = 1024;  // mean keys per partition of R at most this
-constexpr uint32_t kSjMaxFan = 64;
+constexpr uint32_t kSjMaxFan = 256;
 constexpr uint32_t kSjSortCap = 4096;
 constexpr uint32_t kSjMaxPasses = 4;
 struct SortJoinWs {

@@ -71,9 +71,8 @@ def test_random_heavy_duplicates(seed):
 
 @pytest.mark.parametrize("n", [2**18, 2**20, 2**22])
 def test_partition_sizes_span_every_sort_path(n):
-    # Mean partition sizes of about 64, 256 and 1024 keys: the partitions
-    # spread over every wave sort width (64 .. 2048 keys) and, at 2^22, the
-    # block sort beyond 2048 keys.
+    # Mean partition sizes of about 256 and 1024 keys: the partitions spread
+    # over the wave sort widths from 64 to 2048 keys.
     rng = np.random.default_rng(n)
     R = rng.integers(0, 2**62, n, dtype=np.uint64)
     S = np.concatenate([R[rng.integers(0, n, n // 4)],
@@ -96,12 +95,13 @@ def test_edge_cases():
     sort_parity(up[::-1].copy(), "reversed input")
 
 
-@pytest.mark.parametrize("cluster", [6000, 16384])
+@pytest.mark.parametrize("cluster", [3000, 6000, 16384])
 def test_cluster_missed_by_the_sample(cluster):
     # n = 2 * 16384: the model samples the even positions only.  `cluster`
     # odd positions hold distinct keys of one narrow range, in random order,
-    # between two sampled keys: one partition larger than the LDS sort takes
-    # (6000: sorted in LDS by a larger block; 16384: in global memory).
+    # between two sampled keys: one partition larger than the wave sorts take
+    # (3000: sorted in LDS by a block; 6000: in LDS by a larger block; 16384:
+    # in global memory).
     rng = np.random.default_rng(3)
     n = 2 * 16384
     R = rng.integers(0, 2**40, n, dtype=np.uint64) * np.uint64(2**20)
