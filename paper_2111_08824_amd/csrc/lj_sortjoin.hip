@@ -32,7 +32,7 @@ constexpr int kWaves = kBlock / 64;
 constexpr uint32_t kWaveSpan = kPartChunk / kWaves;
 constexpr int kModelThreads = 1024;
 constexpr int kBigThreads = 1024;
-constexpr int kJoinItems = 8;
+constexpr int kJoinItems = 16;
 
 __device__ inline uint32_t sj_digit(uint32_t pid, uint32_t shift) {
     return (pid >> shift) & (kDigits - 1);
@@ -336,7 +336,7 @@ __device__ inline bool sj_less(uint64_t ka, uint32_t pa, uint64_t kb, uint32_t p
 
 template <int E>
 __device__ void sj_sort_wave(uint64_t* __restrict__ keys, uint32_t* __restrict__ pos,
-                             uint32_t sz, uint32_t lane) {
+                             uint32_t sz, uint32_t lane, uint32_t a, uint64_t* __restrict__ rs) {
     uint64_t k[E];
     uint32_t p[E];
 #pragma unroll
@@ -428,32 +428,44 @@ __device__ void sj_sort_wave(uint64_t* __restrict__ keys, uint32_t* __restrict__
         if (e < sz) {
             keys[e] = k[r];
             pos[e] = p[r];
+            if ((a + e) % kLineKeys == 0) rs[(a + e) / kLineKeys] = k[r];
         }
     }
 }
 
 // One wave per partition of kLo + 1 .. kHi keys (kHi <= 1024, or the
 // 2048-key sort alone: its 32 elements per lane need about twice the
-// registers, which would halve the occupancy of the smaller sorts).
+// registers, which would halve the occupancy of the smaller sorts).  Every
+// sort also writes the line samples rs[j] = sorted key kLineKeys * j of its
+// partition (the kLo = 0 launch those of one-key partitions too).
 constexpr uint32_t kSjWaveCap = 2048;
 template <uint32_t kLo, uint32_t kHi>
 __global__ __launch_bounds__(kBlock) void sj_sort_wave_kernel(uint64_t* __restrict__ keys,
                                                               uint32_t* __restrict__ pos,
                                                               const uint32_t* __restrict__ start,
-                                                              uint32_t parts) {
+                                                              uint32_t parts,
+                                                              uint64_t* __restrict__ rs) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t waves = gridDim.x * (kBlock / 64);
     for (uint32_t p = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); p < parts; p += waves) {
         const uint32_t a = start[p], sz = start[p + 1] - a;
-        if (sz <= kLo || sz > kHi || sz <= 1) continue;
+        if (sz <= kLo || sz > kHi || sz == 0) continue;
         if constexpr (kHi > 1024) {
-            sj_sort_wave<32>(keys + a, pos + a, sz, lane);
+            sj_sort_wave<32>(keys + a, pos + a, sz, lane, a, rs);
         } else {
-            if (sz <= 64) sj_sort_wave<1>(keys + a, pos + a, sz, lane);
-            else if (sz <= 128) sj_sort_wave<2>(keys + a, pos + a, sz, lane);
-            else if (sz <= 256) sj_sort_wave<4>(keys + a, pos + a, sz, lane);
-            else if (sz <= 512) sj_sort_wave<8>(keys + a, pos + a, sz, lane);
-            else sj_sort_wave<16>(keys + a, pos + a, sz, lane);
+            if (sz == 1) {
+                if (lane == 0 && a % kLineKeys == 0) rs[a / kLineKeys] = keys[a];
+            } else if (sz <= 64) {
+                sj_sort_wave<1>(keys + a, pos + a, sz, lane, a, rs);
+            } else if (sz <= 128) {
+                sj_sort_wave<2>(keys + a, pos + a, sz, lane, a, rs);
+            } else if (sz <= 256) {
+                sj_sort_wave<4>(keys + a, pos + a, sz, lane, a, rs);
+            } else if (sz <= 512) {
+                sj_sort_wave<8>(keys + a, pos + a, sz, lane, a, rs);
+            } else {
+                sj_sort_wave<16>(keys + a, pos + a, sz, lane, a, rs);
+            }
         }
     }
 }
@@ -464,7 +476,8 @@ __global__ __launch_bounds__(kBlock) void sj_sort_kernel(uint64_t* __restrict__ 
                                                          uint32_t* __restrict__ pos,
                                                          const uint32_t* __restrict__ start,
                                                          uint32_t parts,
-                                                         uint32_t* __restrict__ big) {
+                                                         uint32_t* __restrict__ big,
+                                                         uint64_t* __restrict__ rs) {
     __shared__ uint64_t sk[kSjSortCap];
     __shared__ uint32_t sp[kSjSortCap];
     const uint32_t tid = threadIdx.x;
@@ -484,6 +497,7 @@ __global__ __launch_bounds__(kBlock) void sj_sort_kernel(uint64_t* __restrict__ 
         for (uint32_t i = tid; i < sz; i += kBlock) {
             keys[a + i] = sk[i];
             pos[a + i] = sp[i];
+            if ((a + i) % kLineKeys == 0) rs[(a + i) / kLineKeys] = sk[i];
         }
         __syncthreads();
     }
@@ -496,7 +510,8 @@ __global__ __launch_bounds__(kBlock) void sj_sort_kernel(uint64_t* __restrict__ 
 constexpr uint32_t kBigCap = 10240;
 __global__ __launch_bounds__(kBigThreads) void sj_sort_big_kernel(
     uint64_t* __restrict__ keys, uint32_t* __restrict__ pos,
-    const uint32_t* __restrict__ start, const uint32_t* __restrict__ big) {
+    const uint32_t* __restrict__ start, const uint32_t* __restrict__ big,
+    uint64_t* __restrict__ rs) {
     __shared__ uint64_t sk[kBigCap];
     __shared__ uint32_t sp[kBigCap];
     __shared__ int unsorted;
@@ -524,9 +539,13 @@ __global__ __launch_bounds__(kBigThreads) void sj_sort_big_kernel(
             for (uint32_t i = tid; i < sz; i += kBigThreads) {
                 keys[a + i] = sk[i];
                 pos[a + i] = sp[i];
+                if ((a + i) % kLineKeys == 0) rs[(a + i) / kLineKeys] = sk[i];
             }
-        } else if (work) {
-            sj_bitonic(keys + a, pos + a, sz, tid, kBigThreads);
+        } else {
+            if (work) sj_bitonic(keys + a, pos + a, sz, tid, kBigThreads);
+            for (uint32_t i = (kLineKeys - a % kLineKeys) % kLineKeys + tid * kLineKeys; i < sz;
+                 i += kBigThreads * kLineKeys)
+                rs[(a + i) / kLineKeys] = keys[a + i];
         }
         __syncthreads();
     }
@@ -762,15 +781,16 @@ hipError_t learned_sort(const uint64_t* keys, uint64_t n, uint64_t* keys_out, ui
     hipLaunchKernelGGL(sj_bounds_kernel, dim3(grid_of(num_tiles(n + 1, kBlock), 8192)),
                        dim3(kBlock), 0, stream, pids, n, L.parts, start);
     uint32_t* big = (uint32_t*)(w + L.big_queue);
+    uint64_t* rs = (uint64_t*)(w + L.r_rs);
     const dim3 wgrid(grid_of(num_tiles(L.parts, kBlock / 64), 16384));
     hipLaunchKernelGGL((sj_sort_wave_kernel<0, 1024>), wgrid, dim3(kBlock), 0, stream, keys_out,
-                       pos_out, (const uint32_t*)start, L.parts);
+                       pos_out, (const uint32_t*)start, L.parts, rs);
     hipLaunchKernelGGL((sj_sort_wave_kernel<1024, kSjWaveCap>), wgrid, dim3(kBlock), 0, stream,
-                       keys_out, pos_out, (const uint32_t*)start, L.parts);
+                       keys_out, pos_out, (const uint32_t*)start, L.parts, rs);
     hipLaunchKernelGGL(sj_sort_kernel, dim3(grid_of(L.parts, 16384)), dim3(kBlock), 0, stream,
-                       keys_out, pos_out, (const uint32_t*)start, L.parts, big);
+                       keys_out, pos_out, (const uint32_t*)start, L.parts, big, rs);
     hipLaunchKernelGGL(sj_sort_big_kernel, dim3(256), dim3(kBigThreads), 0, stream, keys_out,
-                       pos_out, (const uint32_t*)start, (const uint32_t*)big);
+                       pos_out, (const uint32_t*)start, (const uint32_t*)big, rs);
     return hipGetLastError();
 }
 
@@ -826,9 +846,7 @@ hipError_t launch_sort_join(const uint64_t* r, uint64_t n, const uint64_t* s, ui
     const uint32_t ntiles = (uint32_t)num_tiles(m, (uint64_t)kBlock * kJoinItems);
     const uint32_t tpx = (uint32_t)num_tiles(ntiles, kXcds);
     uint32_t* runs = (uint32_t*)(w + L.big_queue) + 1 + L.parts;
-    uint64_t* rs = (uint64_t*)(w + L.r_rs);
-    e = launch_line_samples(rk, n, rs, stream);
-    if (e != hipSuccess) return e;
+    const uint64_t* rs = (const uint64_t*)(w + L.r_rs);  // written by the sort
     hipLaunchKernelGGL(sj_join_kernel, dim3(tpx * kXcds), dim3(kBlock), 0, stream, sk, spid, m,
                        (const uint64_t*)rk, (const uint64_t*)rs, (const uint32_t*)rp,
                        (const uint32_t*)(w + L.r_start), ntiles, tpx, res2, runs);
