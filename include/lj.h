@@ -529,7 +529,7 @@ int lj_hash_buckets_host(const lj_index* index, uint64_t* keys_host,
  *                 UINT64_MAX if a kernel hit its internal wait bound.
  *   workspace_dev caller-owned device scratch of at least
  *                 lj_sort_join_workspace_bytes(n, m) bytes (about
- *                 40 n + 32 m bytes), 256-byte aligned; calls sharing one
+ *                 33 n + 32 m bytes), 256-byte aligned; calls sharing one
  *                 workspace must be ordered on one stream.
  *
  * The benchmark timing hook (lj_probe_set_timing_events) brackets the join

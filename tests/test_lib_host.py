@@ -178,3 +178,46 @@ def test_root_is_monotone_and_covers_leaves():
     leaf, _, _, _ = lj.lj_predict_windows_host(ix, R)
     assert np.all(np.diff(leaf.astype(np.int64)) >= 0)
     assert ix.stats.nonempty_leaves == 4096
+
+
+def test_sort_join_workspace_and_argument_checks():
+    """Learned sort join (Section IV): the workspace grows linearly (about
+    33 bytes per key of R and 32 per key of S, plus the model and the
+    per-partition tables), and the host-side checks answer before any
+    device work (fake device addresses are never dereferenced)."""
+    ws = lj.lj_sort_join_workspace_bytes
+    for n, m in ((1, 1), (1000, 5000), (2 * 10**8, 2 * 10**8)):
+        b = ws(n, m)
+        assert 32 * n + 32 * m <= b <= 33 * n + 32 * m + 8 * 2**20, (n, m, b)
+    assert ws(10**6, 0) < ws(10**6, 10**6)
+    assert ws(2 * 10**6, 10) > ws(10**6, 10)
+    L = lj.lib()
+    fake = ctypes.c_void_p(1 << 40)
+    cnt = ctypes.c_void_p(1 << 41)
+    # Null count, null keys with non-zero sizes, output capacity without a buffer.
+    assert L.lj_sort_join_async(fake, 10, fake, 10, None, 0, None, fake, 1 << 20, None) \
+        == lj.LJ_ERR_ARG
+    assert L.lj_sort_join_async(None, 10, fake, 10, None, 0, cnt, fake, 1 << 20, None) \
+        == lj.LJ_ERR_ARG
+    assert L.lj_sort_join_async(fake, 10, None, 10, None, 0, cnt, fake, 1 << 20, None) \
+        == lj.LJ_ERR_ARG
+    assert L.lj_sort_join_async(fake, 10, fake, 10, None, 5, cnt, fake, 1 << 20, None) \
+        == lj.LJ_ERR_ARG
+    # Sizes beyond the index types.
+    assert L.lj_sort_join_async(fake, 2**31, fake, 10, None, 0, cnt, fake, 1 << 20, None) \
+        == lj.LJ_ERR_TOO_LARGE
+    assert L.lj_sort_join_async(fake, 10, fake, 2**32, None, 0, cnt, fake, 1 << 20, None) \
+        == lj.LJ_ERR_TOO_LARGE
+    # Workspace too small, missing or misaligned.
+    need = ws(10, 10)
+    for w, b in ((fake, need - 1), (None, need), (ctypes.c_void_p((1 << 40) + 8), need)):
+        assert L.lj_sort_join_async(fake, 10, fake, 10, None, 0, cnt, w, b, None) \
+            == lj.LJ_ERR_WORKSPACE
+    # The sort alone.
+    assert L.lj_learned_sort_async(None, 10, fake, fake, fake, 1 << 20, None) == lj.LJ_ERR_ARG
+    assert L.lj_learned_sort_async(fake, 10, None, fake, fake, 1 << 20, None) == lj.LJ_ERR_ARG
+    assert L.lj_learned_sort_async(fake, 2**31, fake, fake, fake, 1 << 40, None) \
+        == lj.LJ_ERR_TOO_LARGE
+    assert L.lj_learned_sort_async(fake, 10, fake, fake, fake, ws(10, 0) - 1, None) \
+        == lj.LJ_ERR_WORKSPACE
+    assert L.lj_learned_sort_async(None, 0, None, None, None, 0, None) == lj.LJ_OK
