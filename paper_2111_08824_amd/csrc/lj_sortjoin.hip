@@ -440,7 +440,8 @@ __device__ void sj_sort_wave(uint64_t* __restrict__ keys, uint32_t* __restrict__
 // partition (the kLo = 0 launch those of one-key partitions too).
 constexpr uint32_t kSjWaveCap = 2048;
 template <uint32_t kLo, uint32_t kHi>
-__global__ __launch_bounds__(kBlock) void sj_sort_wave_kernel(uint64_t* __restrict__ keys,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kHi > 1024 ? 3 : 5)))
+void sj_sort_wave_kernel(uint64_t* __restrict__ keys,
                                                               uint32_t* __restrict__ pos,
                                                               const uint32_t* __restrict__ start,
                                                               uint32_t parts,
