@@ -12,8 +12,9 @@
 //              pass per 6-bit digit of the pid, carrying each key's input
 //              position.
 //   sort       (IV-C) each partition is sorted on its own by a bitonic
-//              network over (key, position) in LDS; since the pids are
-//              monotone in the key, R is then globally sorted.
+//              network over (key, position): by one wave in registers, or
+//              by a block in LDS when larger; since the pids are monotone
+//              in the key, R is then globally sorted.
 //   join       (IV-D) S is put in order of its pid's high digits by two
 //              more passes, and each key of S looks up its run in the one
 //              partition of the sorted R that can hold its key (the
