@@ -760,8 +760,9 @@ hipError_t partition_passes(const PassBufs& B, uint64_t n, uint32_t npass, uint3
     return hipSuccess;
 }
 
-// Sorted keys/positions of R end in (keys_out, pos_out); *rk/*rp/*rstart
-// receive where they are and the partition starts.
+// Model, partition passes, partition starts and sorts of R: the sorted keys
+// and their input positions end in (keys_out, pos_out), the partition
+// starts and the line samples in the workspace.
 hipError_t learned_sort(const uint64_t* keys, uint64_t n, uint64_t* keys_out, uint32_t* pos_out,
                         char* w, const SortJoinWs& L, hipStream_t stream) {
     hipLaunchKernelGGL(sj_model_kernel, dim3(1), dim3(kModelThreads), 0, stream, keys, n, L.ns,
