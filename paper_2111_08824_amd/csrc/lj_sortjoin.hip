@@ -699,6 +699,110 @@ __global__ void sj_map_kernel(lj_pair* __restrict__ out, uint64_t cap,
     }
 }
 
+// Emission from the per-key results in S order (res[q] = v | run length
+// << 32), one chunk of kPartChunk keys per block, the chunk's first output
+// rank from the scanned per-chunk pair counts; pairs in (s_idx, r_idx)
+// order, those of rank >= cap not written.  Without runs longer than one
+// (*runs == 0, every R key distinct among the matches) each key emits at
+// most one pair, placed by wave ballots; otherwise the chunk's counts are
+// scanned in LDS and the pairs emitted by a load-balanced loop, a run's
+// k-th pair at v + k.
+__global__ __launch_bounds__(kBlock) void sj_emit_kernel(const uint64_t* __restrict__ res,
+                                                         uint64_t m,
+                                                         const uint64_t* __restrict__ offs,
+                                                         lj_pair* __restrict__ out, uint64_t cap,
+                                                         const uint32_t* __restrict__ runs) {
+    constexpr int kItems = (int)kPartItems;
+    __shared__ uint32_t wsum[kItems * kWaves];
+    __shared__ uint64_t off[kPartChunk + 1];
+    __shared__ uint32_t j0[kPartChunk];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t base = (uint64_t)blockIdx.x * kPartChunk;
+    const uint64_t excl = offs[blockIdx.x];
+    if (excl >= cap) return;
+    uint32_t v[kItems], c[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const uint64_t q = base + (uint64_t)k * kBlock + tid;
+        const uint64_t r = q < m ? res[q] : 0ull;
+        v[k] = (uint32_t)r;
+        c[k] = (uint32_t)(r >> 32);
+    }
+    if (*runs == 0) {
+        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        uint32_t lo[kItems];
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const uint64_t mask = __ballot(c[k] != 0);
+            lo[k] = (uint32_t)__popcll(mask & lt);
+            if (lane == 0) wsum[k * kWaves + wave] = (uint32_t)__popcll(mask);
+        }
+        __syncthreads();
+        uint64_t pre = 0;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            uint32_t wpre = 0;
+            for (int w = 0; w < wave; ++w) wpre += wsum[k * kWaves + w];
+            const uint64_t at = excl + pre + wpre + lo[k];
+            if (c[k] && at < cap) {
+                lj_pair p;
+                p.s_idx = (uint32_t)(base + (uint64_t)k * kBlock + tid);
+                p.r_idx = v[k];
+                out[at] = p;
+            }
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) pre += wsum[k * kWaves + w];
+        }
+        return;
+    }
+    // Chunk order i = k * kBlock + tid: exclusive prefix of the counts.
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        off[k * kBlock + tid] = c[k];
+        j0[k * kBlock + tid] = v[k];
+    }
+    __syncthreads();
+    uint64_t loc[kItems], tsum = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        loc[i] = tsum;
+        tsum += off[tid * kItems + i];
+    }
+    const uint64_t incl = wave_incl_scan(tsum, lane);
+    __shared__ uint64_t wtot[kWaves];
+    if (lane == 63) wtot[wave] = incl;
+    __syncthreads();
+    uint64_t wpre = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        wpre += w < wave ? wtot[w] : 0;
+        total += wtot[w];
+    }
+    const uint64_t texcl = wpre + incl - tsum;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) off[tid * kItems + i] = texcl + loc[i];
+    if (tid == 0) off[kPartChunk] = total;
+    __syncthreads();
+    const uint64_t limit = cap - excl < total ? cap - excl : total;
+    for (uint64_t o = tid; o < limit; o += kBlock) {
+        int a = 0, b = (int)kPartChunk;  // off[kPartChunk] = total > o
+        while (b - a > 1) {
+            const int mid = (a + b) >> 1;
+            if (off[mid] <= o) a = mid;
+            else b = mid;
+        }
+        lj_pair p;
+        p.s_idx = (uint32_t)(base + (uint64_t)a);
+        p.r_idx = j0[a] + (uint32_t)(o - off[a]);
+        out[excl + o] = p;
+    }
+}
+
+// Total pair count, or UINT64_MAX after a wait error.
+__global__ void sj_finish_kernel(const uint64_t* total, const uint32_t* err, uint64_t* count) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *count = *err ? ~0ull : *total;
+}
+
 unsigned grid_of(uint64_t items, uint64_t cap) {
     return (unsigned)(items == 0 ? 1 : items < cap ? items : cap);
 }
@@ -870,8 +974,14 @@ hipError_t launch_sort_join(const uint64_t* r, uint64_t n, const uint64_t* s, ui
     U.counts = L.counts;
     e = launch_unpermute_count(B.dest[0], res1, res0, m, true, ws, U, stream);
     if (e != hipSuccess) return e;
-    e = launch_emit_results(res0, m, (const uint64_t*)(w + L.counts), out, out ? cap : 0,
-                            count_dev, &((WsHeader*)ws)->err, stream);
+    const uint64_t* offs = (const uint64_t*)(w + L.counts);
+    const uint32_t nemit = (uint32_t)num_tiles(m, kPartChunk);
+    if (out && cap)
+        hipLaunchKernelGGL(sj_emit_kernel, dim3(nemit), dim3(kBlock), 0, stream,
+                           (const uint64_t*)res0, m, offs, out, cap, (const uint32_t*)runs);
+    hipLaunchKernelGGL(sj_finish_kernel, dim3(1), dim3(64), 0, stream, offs + nemit,
+                       (const uint32_t*)&((WsHeader*)ws)->err, count_dev);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (out && cap)
         hipLaunchKernelGGL(sj_map_kernel, dim3(4096), dim3(kBlock), 0, stream, out, cap,
