@@ -315,13 +315,6 @@ hipError_t launch_set_u64(uint64_t* p, uint64_t v, hipStream_t stream);
 // num_tiles(n, kScanTile) zeroed words, ctr: a zeroed counter.
 hipError_t launch_scan_u32(uint32_t* d, uint64_t n, uint64_t* status, uint32_t* ctr,
                            uint32_t* err, hipStream_t stream);
-// Emission from per-key results in S order (low word: first position in
-// the sorted R, high word: run length), counts: the per-chunk pair counts'
-// exclusive prefix (+ total) over chunks of kPartChunk keys; writes the total
-// (UINT64_MAX if *err) to count_dev.
-hipError_t launch_emit_results(const uint64_t* res, uint64_t m, const uint64_t* counts,
-                               lj_pair* out, uint64_t cap, uint64_t* count_dev,
-                               const uint32_t* err, hipStream_t stream);
 
 // rs[i] = r[kLineKeys * i] for i < ceil(n / kLineKeys).
 hipError_t launch_line_samples(const uint64_t* r, uint64_t n, uint64_t* rs, hipStream_t stream);

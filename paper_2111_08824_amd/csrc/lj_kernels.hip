@@ -1284,25 +1284,6 @@ hipError_t launch_probe_binned(const lj_index* idx, const uint64_t* s, uint64_t 
 
 }  // namespace
 
-hipError_t launch_emit_results(const uint64_t* res, uint64_t m, const uint64_t* counts,
-                               lj_pair* out, uint64_t cap, uint64_t* count_dev,
-                               const uint32_t* err, hipStream_t stream) {
-    TileJob j{};
-    j.m = m;
-    j.out = out;
-    j.cap = out ? cap : 0;
-    j.count_out = count_dev;
-    j.ntiles = (uint32_t)num_tiles(m, kPartChunk);
-    j.kind = kJobDup;
-    j.kpl = kPartItems;
-    if (m)
-        hipLaunchKernelGGL(emit_chunks_kernel<false>, dim3(j.ntiles), dim3(kBlock), 0, stream, j,
-                           (const void*)res, counts);
-    hipLaunchKernelGGL(finish_binned_kernel, dim3(1), dim3(64), 0, stream, counts + j.ntiles,
-                       err, count_dev);
-    return hipGetLastError();
-}
-
 hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m, lj_pair* out,
                         uint64_t cap, uint64_t* count_dev, void* ws, hipStream_t stream,
                         hipEvent_t ev0, hipEvent_t ev1, uint32_t kpl, int mode) {
