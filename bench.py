@@ -103,6 +103,26 @@ def load_traffic(workload: str, binned: bool, index: str = "rmi"):
         return None
 
 
+def load_step_traffic(workload: str, binned: bool, index: str = "rmi"):
+    """HBM bytes of a whole probe step (every library kernel) from the same
+    counter summary, or None."""
+    kind = ("probe_binned" if binned else "probe") + ("" if index == "rmi" else "_" + index)
+    path = os.path.join(ROOT, "profiles", f"{kind}_{workload}_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["step_bytes"])
+    except (KeyError, ValueError):
+        return None
+
+
 def make_workload(name: str):
     import workloads
     if name == "lognormal-zipf-200M":
@@ -142,15 +162,99 @@ def algorithmic_bytes(pairs_dev, count: int, m: int, out_per_key: float = 0.0,
     return 8.0 * m + 64.0 * sectors + out_per_key * m + out_per_pair * count
 
 
-def cpu_baseline(w, sample: int):
-    import oracle
-    S = w.S[:sample]
+def host_threads() -> int:
+    """Host threads for the oracle's all-cores leg: the CPUs this process may
+    run on, at most 16 (one GPU's share of a GPU machine's host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_slices(fn, jobs, threads: int):
+    """Run fn(job) for every job in `threads` host threads (the oracle's C
+    routines release the interpreter lock); returns (results, seconds)."""
+    from concurrent.futures import ThreadPoolExecutor
     t0 = time.perf_counter()
-    P = oracle.sort_merge_join(w.R, S)
-    dt = time.perf_counter() - t0
-    return {"value": sample / dt, "unit": "probes/s", "cores": 1, "kind": "oracle",
-            "sample": f"sort-merge join of the first {sample} outer keys against all "
-                      f"{len(w.R)} inner keys ({len(P)} pairs) in {dt:.2f} s, one thread"}
+    if threads == 1:
+        out = [fn(j) for j in jobs]
+    else:
+        with ThreadPoolExecutor(threads) as ex:
+            out = list(ex.map(fn, jobs))
+    return out, time.perf_counter() - t0
+
+
+def cpu_baseline(R, S, one_thread_sample: int, threads: int | None = None):
+    """The oracle's sort-merge join, timed on the host: on all host cores
+    (S cut into one contiguous slice per thread, each slice joined with all
+    of R by the unchanged single-threaded oracle; P is the concatenation of
+    the slices' results with s offsets) over all of S, and on one thread
+    over the first `one_thread_sample` keys of S."""
+    import oracle
+    threads = threads or host_threads()
+    m = len(S)
+    cuts = np.linspace(0, m, threads + 1).astype(np.int64)
+    counts, dt = _oracle_slices(lambda ab: len(oracle.sort_merge_join(R, S[ab[0]:ab[1]])),
+                                list(zip(cuts[:-1], cuts[1:])), threads)
+    res = {"value": m / dt, "unit": "probes/s", "cores": threads, "kind": "oracle",
+           "sample": f"sort-merge join of all {m} outer keys against all {len(R)} inner keys "
+                     f"({sum(counts)} pairs) in {dt:.2f} s, S cut into {threads} slices joined "
+                     f"in {threads} host threads"}
+    k = min(one_thread_sample, m)
+    if k:
+        t0 = time.perf_counter()
+        P = oracle.sort_merge_join(R, S[:k])
+        dt1 = time.perf_counter() - t0
+        res["one_thread"] = {"value": k / dt1, "unit": "probes/s", "cores": 1,
+                             "sample": f"first {k} outer keys against all {len(R)} inner keys "
+                                       f"({len(P)} pairs) in {dt1:.2f} s"}
+    return res
+
+
+def measure_bw_rand(stream, gib: int = 4, granule: int = 64, reads: int = 1 << 28) -> dict:
+    """Random-access ceiling on this GPU: lj_bench_random_gather reads
+    `reads` 8-byte words, each from a pseudo-random `granule`-byte granule of
+    a `gib`-GiB buffer; median of 3 timed launches.  BW_rand counts the whole
+    granule per read (the 64-byte sector a probe's search must fetch)."""
+    import torch
+    from paper_2111_08824_amd import lj
+    buf = torch.empty(gib << 30, dtype=torch.uint8, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int64, device="cuda")
+    lj.lj_bench_random_gather(buf, granule, reads, 1, sink, stream)
+    times = []
+    for r in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        lj.lj_bench_random_gather(buf, granule, reads, 2 + r, sink, stream)
+        b.record(stream)
+        b.synchronize()
+        times.append(a.elapsed_time(b) * 1e-3)
+    del buf
+    t = float(np.median(times))
+    return {"gbs": round(reads * granule / t / 1e9, 1), "loads_per_s": reads / t,
+            "buffer_gib": gib, "granule": granule, "reads": reads}
+
+
+def random_roofline(value: float, b_probe: float, bw: dict) -> dict:
+    """Probes/s ceiling of the random-access roofline (BW_rand / B_probe) and
+    the fraction of it reached."""
+    roof = bw["gbs"] * 1e9 / b_probe
+    return {"bw_rand_gbs": bw["gbs"], "b_probe": round(b_probe, 3),
+            "random_roofline_probes_per_s": roof, "frac_random": round(value / roof, 4),
+            "nominal_roofline_probes_per_s": HBM_PEAK_GBS * 1e9 / b_probe}
+
+
+def latency_reps(step, reps: int):
+    """p50 / p99 of `reps` synchronous steps (milliseconds)."""
+    lat = []
+    for _ in range(reps):
+        a = time.perf_counter()
+        step()
+        lat.append(time.perf_counter() - a)
+    lat_ms = np.array(lat) * 1e3
+    return {"p50": round(float(np.percentile(lat_ms, 50)), 4),
+            "p99": round(float(np.percentile(lat_ms, 99)), 4), "reps": reps}
 
 
 def cpu_baseline_sort_join(w, sample: int):
@@ -204,19 +308,17 @@ def bench_sort_join(args) -> None:
         a.record(stream)
         b.record(stream)
     torch.cuda.synchronize()
-    lat = []
     t_start = time.perf_counter()
     for i in range(args.steps):
         lj.lj_probe_set_timing_events(ev[i][0], ev[i][1])
-        a = time.perf_counter()
         count = step()
-        lat.append(time.perf_counter() - a)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     if w.expected_count is not None and count != w.expected_count:
         raise SystemExit(f"pair count {count} != expected {w.expected_count}")
     kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     ms_per_step = wall * 1e3 / args.steps
+    latency = latency_reps(step, max(args.latency_reps, args.steps))
     if args.copy_calibration_mib:
         src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -228,14 +330,22 @@ def bench_sort_join(args) -> None:
     # read, one 64 B sector of the sorted R searched, an 8 B result written.
     alg = 84.0 * m
     achieved = alg / (kern_ms * 1e-3) / 1e9
+    traffic = load_traffic_sort_join(w.name)
+    # A join of two unsorted relations reads each once and writes its pairs:
+    # 8 (n + m) + 8 pairs bytes at the least.
+    step_alg = 8.0 * (n + m) + 8.0 * count
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": load_traffic_sort_join(w.name),
+            "traffic": traffic,
             "algorithmic_bytes_per_launch": alg, "kernel": "sj_join_kernel",
-            "kernel_ms": round(kern_ms, 4)}
-    cpu = (cpu_baseline_sort_join(w, min(args.cpu_sample // 4, n, m)) if args.cpu_sample
+            "kernel_ms": round(kern_ms, 4),
+            "traffic_gbs": round(traffic / (kern_ms * 1e-3) / 1e9, 1) if traffic else None,
+            "step_algorithmic_bytes": step_alg,
+            "frac_step": round(step_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    del ws, out
+    torch.cuda.synchronize()
+    cpu = (cpu_baseline_sort_join(w, min(args.cpu_sample, n, m)) if args.cpu_sample
            else None)
-    lat_ms = np.array(lat) * 1e3
     res = {
         "metric": "join tuples/sec ((|R| + |S|) per second), learned sort join",
         "value": (n + m) / (ms_per_step * 1e-3),
@@ -253,8 +363,7 @@ def bench_sort_join(args) -> None:
                    "pairs": int(count)},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
-                       "p99": round(float(np.percentile(lat_ms, 99)), 4)},
+        "latency_ms": latency,
     }
     print(json.dumps(res), flush=True)
 
@@ -264,9 +373,12 @@ def _json_line(res: dict) -> None:
 
 
 def bench_multi_index(args) -> None:
-    """64 independent indexes, one batch of outer keys each: the plain probe
-    launched batch after batch (synchronous, as a caller would without the
-    batched API) against one autotuned plan replayed from a HIP graph."""
+    """64 independent indexes, one batch of outer keys each, three ways: the
+    plain probe launched batch after batch synchronously (lj_probe_join: a
+    count readback and a stream wait per batch, as a caller without the
+    batched API), the same launches back to back asynchronously on one
+    stream (lj_probe_join_async, one wait at the end: device work only), and
+    one autotuned plan replayed from a HIP graph (the timed value)."""
     import torch
     import workloads
     from paper_2111_08824_amd import lj
@@ -277,7 +389,7 @@ def bench_multi_index(args) -> None:
           f"{sum(len(w.S) for w in ws)} outer keys ({time.perf_counter() - t0:.1f} s)",
           file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
-    batches, expected = [], []
+    batches, expected, wspaces = [], [], []
     for w in ws:
         ix = lj.lj_build_rmi(w.R, w.leaves, lj.LJ_LEAF_FP32, stream)
         s = lj.to_device_keys(w.S)
@@ -285,54 +397,99 @@ def bench_multi_index(args) -> None:
         cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
         batches.append((ix, s, out, cnt))
         expected.append(w.expected_count)
+        wspaces.append(torch.empty(max(256, lj.lj_probe_workspace_bytes(ix, len(w.S))),
+                                   dtype=torch.uint8, device="cuda"))
     m_total = sum(len(w.S) for w in ws)
     torch.cuda.synchronize()
 
-    def plain_once():
+    def plain_sync():
         for ix, s, out, cnt in batches:
             st, c = lj.lj_probe_join(ix, s, out, stream)
             assert st == lj.LJ_OK
 
-    for _ in range(args.warmup):
-        plain_once()
-    torch.cuda.synchronize()
-    a = time.perf_counter()
-    for _ in range(args.steps):
-        plain_once()
-    torch.cuda.synchronize()
-    plain_ms = (time.perf_counter() - a) * 1e3 / args.steps
+    def plain_async():
+        for (ix, s, out, cnt), wsp in zip(batches, wspaces):
+            lj.lj_probe_join_async(ix, s, out, cnt, wsp, stream)
+        stream.synchronize()
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - a) * 1e3 / args.steps
+
+    sync_ms = timed(plain_sync)
+    async_ms = timed(plain_async)
 
     tuning = lj.lj_batch_autotune(batches, stream)
     plan = lj.BatchPlan(batches, tuning)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+
+    def plan_step():
+        plan.run(stream)
+        stream.synchronize()
+
     for _ in range(args.warmup):
-        plan.run(stream)
+        plan_step()
     torch.cuda.synchronize()
-    lat = []
     a = time.perf_counter()
-    for _ in range(args.steps):
-        b = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
         plan.run(stream)
-        torch.cuda.synchronize()
-        lat.append(time.perf_counter() - b)
+        ev[i][1].record(stream)
+        stream.synchronize()
     plan_ms = (time.perf_counter() - a) * 1e3 / args.steps
+    dev_ms = float(np.mean([x.elapsed_time(y) for x, y in ev]))
     got = [int(c.item()) for *_, c in batches]
     if got != expected:
         raise SystemExit("batched pair counts differ from the generator's hit counts")
-    lat_ms = np.array(lat) * 1e3
+    latency = latency_reps(plan_step, max(args.latency_reps, args.steps))
+    value = m_total / (plan_ms * 1e-3)
+    alg = sum(algorithmic_bytes(out, c, s.numel()) for (_, s, out, _), c in zip(batches, got))
+    achieved = alg / (dev_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes_per_launch": alg,
+            "kernel": "plan run (graph replay of every batch's probe kernels)",
+            "kernel_ms": round(dev_ms, 4),
+            "frac_step": round(alg / (plan_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if args.diagnostics:
+        roof.update(random_roofline(value, alg / m_total, measure_bw_rand(stream)))
+    plan.close()
+    del wspaces
+    torch.cuda.synchronize()
+    cpu = None
+    if args.cpu_sample:
+        import oracle
+        th = host_threads()
+        order = sorted(range(len(ws)), key=lambda i: -len(ws[i].S))  # longest first
+        counts, dt = _oracle_slices(lambda i: len(oracle.sort_merge_join(ws[i].R, ws[i].S)),
+                                    order, th)
+        cpu = {"value": m_total / dt, "unit": "probes/s", "cores": th, "kind": "oracle",
+               "sample": f"sort-merge join of all 64 batches ({m_total} outer keys, "
+                         f"{sum(counts)} pairs) in {dt:.2f} s, one batch per host thread at "
+                         f"a time, {th} threads"}
     _json_line({
-        "metric": METRIC, "value": m_total / (plan_ms * 1e-3), "unit": "probes/s",
+        "metric": METRIC, "value": value, "unit": "probes/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(plan_ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "multi-index-64", "indexes": 64,
                    "inner_keys": int(sum(len(w.R) for w in ws)), "outer_keys": int(m_total),
-                   "tuning": tuning.as_dict()},
-        "plain_per_batch": {"ms_per_step": round(plain_ms, 4),
-                            "probes_per_s": m_total / (plain_ms * 1e-3)},
-        "speedup_vs_plain": round(plain_ms / plan_ms, 3),
-        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
-                       "p99": round(float(np.percentile(lat_ms, 99)), 4)},
-        "roofline": None, "cpu_baseline": None,
+                   "leaf_model": "fp32", "tuning": tuning.as_dict()},
+        "plain_per_batch_sync": {"ms_per_step": round(sync_ms, 4),
+                                 "probes_per_s": m_total / (sync_ms * 1e-3)},
+        "plain_per_batch_async": {"ms_per_step": round(async_ms, 4),
+                                  "probes_per_s": m_total / (async_ms * 1e-3)},
+        "speedup_vs_plain_sync": round(sync_ms / plan_ms, 3),
+        "speedup_vs_plain_async": round(async_ms / plan_ms, 3),
+        "latency_ms": latency,
+        "roofline": roof, "cpu_baseline": cpu,
     })
 
 
@@ -342,9 +499,11 @@ def bench_serving(args) -> None:
     plain per-request probe, run through the serving loop configured as the
     plain per-request probe (one stream, one request per launch) and as the
     continuously batching server (8 streams, up to 16 requests and 2^22 keys
-    per batch).  --request-buffers device keeps request keys and pairs in
-    HBM (lj_server_submit_device: no PCIe copies) and adds a server
-    configuration that probes requests of 2^20 keys or more binned."""
+    per batch), with and without the binned probe for requests of 2^20 keys
+    or more.  The value is the best served configuration's throughput at
+    saturation (all requests submitted at once).  --request-buffers host
+    puts request keys and pairs in pinned host memory (PCIe copies
+    included) instead of device memory."""
     import threading
     import queue as pyqueue
 
@@ -391,13 +550,15 @@ def bench_serving(args) -> None:
 
     def run(cfg, reqs, rate):
         """Submit reqs (Poisson arrivals at `rate` per second, or all at once
-        when rate is None); returns (wall seconds, latencies in ms)."""
+        when rate is None); returns (wall seconds, latencies in ms, stats,
+        total pairs)."""
         srv = lj.Server(ixs, cfg)
         free = pyqueue.Queue()
         for b in range(nbuf):
             free.put(b)
         tickets = pyqueue.Queue()
         lat = []
+        pairs = [0]
 
         def collector():
             for _ in range(len(reqs)):
@@ -405,6 +566,7 @@ def bench_serving(args) -> None:
                 r = srv.wait(t)
                 assert r.status == lj.LJ_OK
                 lat.append((r.done_ns - r.submit_ns) * 1e-6)
+                pairs[0] += r.count
                 free.put(b)
 
         th = threading.Thread(target=collector)
@@ -427,16 +589,15 @@ def bench_serving(args) -> None:
         wall = time.perf_counter() - start
         st = srv.stats
         srv.close()
-        return wall, np.array(lat), st
+        return wall, np.array(lat), st, pairs[0]
 
     plain = lj.lj_server_default_config(24 << 30)
     plain.slots, plain.max_batch_requests = 1, 1
     served = lj.lj_server_default_config(24 << 30)
-    configs = [("plain_per_request", plain), ("served", served)]
-    if on_device:
-        served_binned = lj.lj_server_default_config(24 << 30)
-        served_binned.binned_min_keys = 1 << 20
-        configs.append(("served_binned", served_binned))
+    served_binned = lj.lj_server_default_config(24 << 30)
+    served_binned.binned_min_keys = 1 << 20
+    configs = [("plain_per_request", plain), ("served", served),
+               ("served_binned", served_binned)]
 
     warm = make_requests(64)
     for _, cfg in configs:
@@ -445,13 +606,13 @@ def bench_serving(args) -> None:
     keys_sat = sum(m for _, _, m in sat_reqs)
     sat = {}
     for name, cfg in configs:
-        wall, _, st = run(cfg, sat_reqs, None)
-        sat[name] = (wall, st)
+        wall, lat, st, pairs = run(cfg, sat_reqs, None)
+        sat[name] = (wall, st, pairs, lat)
         print(f"[bench] saturation {name}: {len(sat_reqs) / wall:.1f} req/s, "
               f"{keys_sat / wall:.3e} probes/s", file=sys.stderr, flush=True)
     w_plain = sat["plain_per_request"][0]
     best = min((n for n, _ in configs if n != "plain_per_request"), key=lambda n: sat[n][0])
-    w_served, st_sat = sat[best]
+    w_served, st_sat, pairs_sat, lat_sat = sat[best]
     sat_rate = len(sat_reqs) / w_plain
     loads = {}
     for load in (0.5, 0.8):
@@ -459,71 +620,126 @@ def bench_serving(args) -> None:
         keys = sum(m for _, _, m in reqs)
         row = {}
         for name, cfg in configs:
-            wall, lat, st = run(cfg, reqs, load * sat_rate)
+            wall, lat, st, _ = run(cfg, reqs, load * sat_rate)
             row[name] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
                          "p99_ms": round(float(np.percentile(lat, 99)), 3),
                          "probes_per_s": keys / wall, "batches": int(st.batches),
                          "max_batch": int(st.max_batch_size)}
             print(f"[bench] load {load} {name}: {row[name]}", file=sys.stderr, flush=True)
         loads[str(load)] = row
+    value = keys_sat / w_served
+    # Every resident R is duplicate-free: one sector of R per outer key, at
+    # most one pair.
+    alg = 72.0 * keys_sat + 8.0 * pairs_sat
+    achieved = alg / w_served / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes_per_launch": alg,
+            "kernel": f"every probe kernel of the {best} configuration at saturation "
+                      "(wall clock)",
+            "kernel_ms": round(w_served * 1e3, 3),
+            "frac_step": round(achieved / HBM_PEAK_GBS, 4)}
+    if args.diagnostics:
+        roof.update(random_roofline(value, alg / keys_sat, measure_bw_rand(
+            torch.cuda.current_stream())))
+        roof["plain_per_request_frac_random"] = round(
+            keys_sat / w_plain / roof["random_roofline_probes_per_s"], 4)
+    cpu = None
+    if args.cpu_sample:
+        import oracle
+        th = host_threads()
+        sample = sat_reqs[:100]
+        counts, dt = _oracle_slices(
+            lambda r: len(oracle.sort_merge_join(ws[r[0]].R, ws[r[0]].S[r[1]:r[1] + r[2]])),
+            sample, th)
+        keys = sum(m for _, _, m in sample)
+        cpu = {"value": keys / dt, "unit": "probes/s", "cores": th, "kind": "oracle",
+               "sample": f"sort-merge join of the first 100 saturation requests ({keys} "
+                         f"outer keys, {sum(counts)} pairs) in {dt:.2f} s, one request per "
+                         f"host thread at a time, {th} threads"}
     _json_line({
-        "metric": METRIC, "value": keys_sat / w_served, "unit": "probes/s",
+        "metric": METRIC, "value": value, "unit": "probes/s",
         "n_gpus": 1, "steps": len(sat_reqs), "warmup": 0,
         "ms_per_step": round(w_served * 1e3 / len(sat_reqs), 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "serving-8x50M", "indexes": 8, "inner_keys_each": 50_000_000,
+                   "leaf_model": "fp32",
                    "request_keys": "log-uniform 256..4194304", "requests_per_load": nreq,
                    "request_buffers": args.request_buffers, "server": best},
         "saturation": {**{f"{n}_probes_per_s": keys_sat / sat[n][0] for n, _ in configs},
-                       "served_max_batch": int(st_sat.max_batch_size)},
+                       "served_max_batch": int(st_sat.max_batch_size),
+                       "served_speedup_vs_plain": round(w_plain / w_served, 3)},
+        "latency_ms": {"p50": round(float(np.percentile(lat_sat, 50)), 4),
+                       "p99": round(float(np.percentile(lat_sat, 99)), 4),
+                       "reps": len(sat_reqs), "at": "saturation"},
         "loads": loads,
-        "roofline": None, "cpu_baseline": None,
+        "roofline": roof, "cpu_baseline": cpu,
     })
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="lognormal-zipf-200M")
-    ap.add_argument("--leaf", choices=["fp32", "fp64"], default="fp32")
-    ap.add_argument("--search", choices=["binary", "exponential"], default="binary",
-                    help="last-mile search inside the error bounds")
-    ap.add_argument("--probe", choices=["direct", "binned"], default="binned",
-                    help="probe S in its own order, or partitioned by key range first")
-    ap.add_argument("--index", choices=["rmi", "gapped", "hash"], default="rmi",
-                    help="plain RMI over R, gapped RMI (model-based insertion), or "
-                         "learned hash (the RMI as hash function of a bucket-chained table)")
-    ap.add_argument("--slots-per-key", type=int, default=4,
-                    help="gapped RMI or learned hash: slots per key of R")
-    ap.add_argument("--join", choices=["inlj", "lsj"], default="inlj",
-                    help="learned indexed nested loop join (index on sorted R), or the "
-                         "learned sort join of R shuffled and S")
-    ap.add_argument("--cpu-sample", type=int, default=120_000_000,
-                    help="outer keys in the timed oracle sample (0 = skip)")
-    ap.add_argument("--requests", type=int, default=1000,
-                    help="requests per load level in the serving workload")
-    ap.add_argument("--request-buffers", choices=["host", "device"], default="host",
-                    help="serving workload: request keys and pairs in pinned host memory "
-                         "(copied over PCIe) or already in device memory")
-    ap.add_argument("--copy-calibration-mib", type=int, default=0,
-                    help="after the steps, run a plain device copy of this many MiB "
-                         "(reference point for HBM byte counters)")
-    args = ap.parse_args()
+def search_diagnostics(ix, R, S, sample: int = 1_000_000, seed: int = 5) -> dict:
+    """Model-quality cost of the last-mile search, exactly on the host for a
+    sample of the outer keys: the window the index gives each key
+    (lj_predict_windows_host, the host copy of the model), then a textbook
+    lower_bound over that window of R, counting its probes and the distinct
+    64-byte sectors of R they touch (sigma-bar: the paper's last-mile search
+    steps, turned into memory sectors)."""
+    from paper_2111_08824_amd import lj
+    rng = np.random.default_rng(seed)
+    k = min(sample, len(S))
+    xs = S[rng.choice(len(S), k, replace=False)] if k < len(S) else S
+    _, _, lo, hi = lj.lj_predict_windows_host(ix, xs)
+    first = np.where(lo <= hi, lo, 0).astype(np.int64)
+    win = np.where(lo <= hi, hi - lo + 1, 0).astype(np.int64)
+    length = win.copy()
+    sect = []
+    steps = np.zeros(k, dtype=np.int64)
+    while True:
+        act = length > 0
+        if not act.any():
+            break
+        half = length >> 1
+        mid = np.where(act, first + half, 0)
+        sect.append(np.where(act, mid // 8, -1))
+        steps += act
+        lt = act & (R[mid] < xs)
+        first = np.where(lt, mid + 1, first)
+        length = np.where(act, np.where(lt, length - half - 1, half), 0)
+    if sect:
+        a = np.sort(np.stack(sect), axis=0)
+        distinct = ((a[1:] != a[:-1]) & (a[1:] >= 0)).sum(axis=0) + (a[0] >= 0)
+    else:
+        distinct = np.zeros(k, dtype=np.int64)
+    return {"sample_keys": int(k), "mean_search_steps": round(float(steps.mean()), 3),
+            "sigma_bar_sectors": round(float(distinct.mean()), 3),
+            "mean_window_of_sample": round(float(win.mean()), 2)}
 
-    if args.gpus != 1:
-        print(json.dumps({"error": "the probe runs on one GPU; --gpus must be 1",
-                          "n_gpus": args.gpus}), flush=True)
-        sys.exit(2)
 
-    if args.workload == "multi-index-64":
-        return bench_multi_index(args)
-    if args.workload == "serving-8x50M":
-        return bench_serving(args)
-    if args.join == "lsj":
-        return bench_sort_join(args)
+def infinite_cache_floor(R, s_dev, out, count: int, m: int) -> dict | None:
+    """Compulsory bytes with unlimited cache reuse: 8 B per outer key, one
+    64-byte sector of R per distinct sector that any key's insertion point or
+    match run falls in (Zipf reuse makes many keys share one), 8 B per pair.
+    Positions come from a sorted search of all outer keys in R on the device
+    (a diagnostic outside the probe; it needs every key below 2^63, where
+    int64 order is uint64 order)."""
+    import torch
+    from paper_2111_08824_amd import lj
+    if (len(R) and int(R[-1]) >= 2**63) or m == 0:
+        return None
+    r_dev = lj.to_device_keys(R)
+    if int(s_dev.min().item()) < 0:
+        return None
+    pos = torch.searchsorted(r_dev, s_dev)
+    sec = torch.clamp(pos, max=max(len(R) - 1, 0)) // 8
+    if count:
+        sec = torch.cat([sec, out[:count, 1].to(torch.int64) // 8])
+    distinct = int(torch.unique(sec).numel())
+    del r_dev, pos, sec
+    floor = 8.0 * m + 64.0 * distinct + 8.0 * count
+    return {"distinct_sectors": distinct, "floor_bytes": floor, "floor_b_probe": floor / m}
 
+
+def bench_inlj(args) -> None:
     import torch
     from paper_2111_08824_amd import lj
 
@@ -558,9 +774,13 @@ def main():
           f"window {st.max_window}, nonempty leaves {st.nonempty_leaves}, device bytes "
           f"{st.device_bytes}", file=sys.stderr, flush=True)
 
-    for _ in range(args.warmup):
+    def step():
         status, count = lj.lj_probe_join(ix, s_dev, out, stream)
         assert status == lj.LJ_OK
+        return count
+
+    for _ in range(args.warmup):
+        step()
     torch.cuda.synchronize()
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -568,21 +788,21 @@ def main():
     for a, b in ev:  # materialise the HIP events; the library re-records them
         a.record(stream)
         b.record(stream)
-    lat = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
         lj.lj_probe_set_timing_events(ev[i][0], ev[i][1])
-        a = time.perf_counter()
-        status, count = lj.lj_probe_join(ix, s_dev, out, stream)
-        lat.append(time.perf_counter() - a)
+        count = step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    assert status == lj.LJ_OK
     if w.expected_count is not None and count != w.expected_count:
         raise SystemExit(f"pair count {count} != expected {w.expected_count}")
     kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     ms_per_step = wall * 1e3 / args.steps
+    value = m / (ms_per_step * 1e-3)
+    print(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms per step, timed kernel "
+          f"{kern_ms:.3f} ms", file=sys.stderr, flush=True)
+    latency = latency_reps(step, max(args.latency_reps, args.steps))
 
     if args.copy_calibration_mib:
         src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device="cuda")
@@ -593,30 +813,66 @@ def main():
         del src, dst
 
     slot_bytes = 16 if gapped or hashed else 8
-    if binned:  # search kernel: keys in, one 4-byte (8 with duplicates) result out
+    # The method's compulsory bytes per step (8 B per outer key, the R
+    # sectors of its insertion point or match run, 8 B per pair), and those
+    # of the timed kernel: for the binned probe its search (a 4- or 8-byte
+    # result per key, no pairs).
+    step_alg = algorithmic_bytes(out, int(count), m, slot_bytes=slot_bytes)
+    if binned:
         alg = algorithmic_bytes(out, int(count), m, 4.0 if st.max_mult <= 1 else 8.0, 0.0,
                                 slot_bytes)
     else:
-        alg = algorithmic_bytes(out, int(count), m, slot_bytes=slot_bytes)
+        alg = step_alg
     achieved = alg / (kern_ms * 1e-3) / 1e9
+    # The counter summaries were taken with FP32 leaves, binary search and
+    # the default slots per key.
+    summary_ok = (args.leaf == "fp32" and args.search == "binary"
+                  and (args.index == "rmi" or args.slots_per_key == 4))
+    traffic = load_traffic(w.name, binned, args.index) if summary_ok else None
+    step_traffic = load_step_traffic(w.name, binned, args.index) if summary_ok else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            # The counter summaries were taken with FP32 leaves, binary search
-            # and the default slots per key.
-            "traffic": (load_traffic(w.name, binned, args.index)
-                        if args.leaf == "fp32" and args.search == "binary"
-                        and (args.index == "rmi" or args.slots_per_key == 4) else None),
+            "traffic": traffic,
             "algorithmic_bytes_per_launch": alg,
             "kernel": (("probe_binned_gapped_kernel+gapped_queue_kernel"
                         if gapped and st.max_mult <= 1 else "probe_binned_kernel")
                        if binned else "probe_join_kernel"),
-            "kernel_ms": round(kern_ms, 4)}
+            "kernel_ms": round(kern_ms, 4),
+            "traffic_gbs": round(traffic / (kern_ms * 1e-3) / 1e9, 1) if traffic else None,
+            "step_algorithmic_bytes": step_alg,
+            "frac_step": round(step_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "step_traffic": step_traffic}
+    diag = {}
+    if args.diagnostics:
+        bw = measure_bw_rand(stream)
+        roof.update(random_roofline(value, step_alg / m, bw))
+        roof["bw_rand_loads_per_s"] = bw["loads_per_s"]
+        if not gapped and not hashed:
+            # Pred / Srch split (the paper's runtime breakdown): a kernel that
+            # only routes, reads the leaf record and computes the window of
+            # every outer key (one 8-byte store per key), in S order.
+            wlo = torch.empty(m, dtype=torch.int64, device="cuda")
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            lj.lj_predict_windows(ix, s_dev, None, None, wlo, None, stream)
+            a.record(stream)
+            lj.lj_predict_windows(ix, s_dev, None, None, wlo, None, stream)
+            b.record(stream)
+            b.synchronize()
+            diag["predict_only_ms"] = round(a.elapsed_time(b), 4)
+            del wlo
+            diag.update(search_diagnostics(ix, w.R, w.S))
+        fl = infinite_cache_floor(w.R, s_dev, out, int(count), m)
+        if fl:
+            diag.update(fl)
+            roof["frac_step_floor"] = round(fl["floor_bytes"] / (ms_per_step * 1e-3) / 1e9
+                                            / HBM_PEAK_GBS, 4)
+    del out
+    torch.cuda.synchronize()
 
-    cpu = cpu_baseline(w, min(args.cpu_sample, m)) if args.cpu_sample else None
-    lat_ms = np.array(lat) * 1e3
+    cpu = (cpu_baseline(w.R, w.S, min(args.cpu_sample, m)) if args.cpu_sample else None)
     res = {
         "metric": METRIC,
-        "value": m / (ms_per_step * 1e-3),
+        "value": value,
         "unit": "probes/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -638,11 +894,62 @@ def main():
                    "mean_window": round(st.mean_window, 2), "max_window": int(st.max_window)},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
-                       "p99": round(float(np.percentile(lat_ms, 99)), 4)},
+        "latency_ms": latency,
         "join_tuples_per_s": (len(w.R) + m) / (ms_per_step * 1e-3),
+        "diagnostics": diag or None,
     }
     print(json.dumps(res), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="lognormal-zipf-200M")
+    ap.add_argument("--leaf", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--search", choices=["binary", "exponential"], default="binary",
+                    help="last-mile search inside the error bounds")
+    ap.add_argument("--probe", choices=["direct", "binned"], default="binned",
+                    help="probe S in its own order, or partitioned by key range first")
+    ap.add_argument("--index", choices=["rmi", "gapped", "hash"], default="rmi",
+                    help="plain RMI over R, gapped RMI (model-based insertion), or "
+                         "learned hash (the RMI as hash function of a bucket-chained table)")
+    ap.add_argument("--slots-per-key", type=int, default=4,
+                    help="gapped RMI or learned hash: slots per key of R")
+    ap.add_argument("--join", choices=["inlj", "lsj"], default="inlj",
+                    help="learned indexed nested loop join (index on sorted R), or the "
+                         "learned sort join of R shuffled and S")
+    ap.add_argument("--cpu-sample", type=int, default=30_000_000,
+                    help="outer keys in the one-thread oracle sample (0 = skip both "
+                         "oracle legs); the all-cores leg joins the whole workload")
+    ap.add_argument("--latency-reps", type=int, default=100,
+                    help="synchronous steps behind p50 / p99 (at least --steps)")
+    ap.add_argument("--no-diagnostics", dest="diagnostics", action="store_false",
+                    help="skip BW_rand, the predict-only timing, sigma-bar and the "
+                         "infinite-cache floor")
+    ap.add_argument("--requests", type=int, default=1000,
+                    help="requests per load level in the serving workload")
+    ap.add_argument("--request-buffers", choices=["host", "device"], default="device",
+                    help="serving workload: request keys and pairs already in device "
+                         "memory, or in pinned host memory (copied over PCIe)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after the steps, run a plain device copy of this many MiB "
+                         "(reference point for HBM byte counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "the probe runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    if args.workload == "multi-index-64":
+        return bench_multi_index(args)
+    if args.workload == "serving-8x50M":
+        return bench_serving(args)
+    if args.join == "lsj":
+        return bench_sort_join(args)
+    return bench_inlj(args)
 
 
 if __name__ == "__main__":

@@ -221,6 +221,10 @@ void lj_server::schedule_loop() {
         }
         lk.unlock();
         hipError_t e = enqueue_batch(free_slot);
+        // After a failure part of the batch may already be enqueued: let it
+        // finish before the completion thread releases the batch's arena
+        // ranges (it skips the per-request waits of failed requests).
+        if (e != hipSuccess) (void)hipStreamSynchronize(free_slot->stream);
         lk.lock();
         if (e != hipSuccess) {
             for (Request* r : batch) r->res.status = LJ_ERR_DEVICE;

@@ -33,3 +33,36 @@ def test_algorithmic_bytes_definition():
     assert bench.algorithmic_bytes(pairs, 6, 3, 4.0, 0.0) == 8 * 3 + 64 * sectors + 4 * 3
     # Gapped slots (16 bytes): 4 slots per sector, so r 5..9 spans 2 sectors.
     assert bench.algorithmic_bytes(pairs, 6, 3, slot_bytes=16) == 8 * 3 + 64 * (3 + 1) + 8 * 6
+
+
+def test_search_diagnostics_count_probes_and_sectors():
+    """sigma-bar and the step count of the benchmark's diagnostics equal a
+    one-key-at-a-time textbook lower_bound over each key's window, written
+    out here with a set of the 64-byte sectors it reads."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import workloads
+    from paper_2111_08824_amd import lj
+    w = workloads.c2_lognormal_zipf(scale=0.0005)
+    ix = lj.lj_build_rmi_host_only(w.R, w.leaves, lj.LJ_LEAF_FP32)
+    d = bench.search_diagnostics(ix, w.R, w.S, sample=300, seed=3)
+    rng = np.random.default_rng(3)
+    xs = w.S[rng.choice(len(w.S), 300, replace=False)]
+    _, _, lo, hi = lj.lj_predict_windows_host(ix, xs)
+    steps, sectors = [], []
+    for x, a, b in zip(xs, lo, hi):
+        first, n, seen, k = int(a), int(b - a + 1) if a <= b else 0, set(), 0
+        while n > 0:
+            half = n // 2
+            mid = first + half
+            seen.add(mid // 8)
+            k += 1
+            if w.R[mid] < x:
+                first, n = mid + 1, n - half - 1
+            else:
+                n = half
+        steps.append(k)
+        sectors.append(len(seen))
+    assert d["sample_keys"] == 300
+    assert abs(d["mean_search_steps"] - np.mean(steps)) < 1e-3
+    assert abs(d["sigma_bar_sectors"] - np.mean(sectors)) < 1e-3

@@ -1,8 +1,8 @@
 """Full-size parity on the lognormal / Zipf workload (2e8 x 2e8, 2^20 leaves),
-probed the way the benchmark probes it (FP32 leaves, synchronous probe, with
-and without the binned probe, on a plain RMI and on a gapped RMI with 4
-slots per key); and the sequential-with-holes workload (2e8 x 2e8) on the
-learned hash index and the plain RMI.
+probed the way the benchmark probes it (synchronous probe, with and without
+the binned probe; FP32 and FP64 leaf models on a plain RMI, FP32 on a gapped
+RMI with 4 slots per key); and the sequential-with-holes workload (2e8 x 2e8)
+on the learned hash index and the plain RMI.
 
 The oracle's full sort-merge is too slow on the host at this size, so the
 output is checked by properties that pin it exactly:
@@ -26,13 +26,17 @@ BIN = lj.LJ_PROBE_BINNED
 # (flags, index kind, slots per key)
 MODES = [(lj.LJ_LEAF_FP32, "rmi", 0), (lj.LJ_LEAF_FP32 | BIN, "rmi", 0),
          (lj.LJ_LEAF_FP32, "gapped", 4), (lj.LJ_LEAF_FP32 | BIN, "gapped", 4)]
+# The FP64 leaf model of the same index: the other half of the FP32 / FP64
+# comparison at full size (48-byte leaf records, f64 windows).
+FP64_MODES = [(lj.LJ_LEAF_FP64, "rmi", 0), (lj.LJ_LEAF_FP64 | BIN, "rmi", 0)]
 HASH_MODES = [(lj.LJ_LEAF_FP32, "hash", 4), (lj.LJ_LEAF_FP32 | BIN, "hash", 4),
               (lj.LJ_LEAF_FP32 | BIN, "rmi", 0)]
 
 
 def build(w, mode):
     flags, kind, spk = mode
-    print(f"[fullsize] building {kind} index (fp32 leaves, {w.leaves}, flags {flags}, "
+    leaf = "fp64" if flags & lj.LJ_LEAF_FP64 else "fp32"
+    print(f"[fullsize] building {kind} index ({leaf} leaves, {w.leaves}, flags {flags}, "
           f"slots/key {spk})", flush=True)
     if kind == "gapped":
         return lj.lj_build_gapped_rmi(w.R, w.leaves, spk, flags)
@@ -88,7 +92,7 @@ def check_unique_full_size(w, mode, seed):
     assert np.array_equal(ri[pos_c][emitted], first[emitted].astype(np.int64))
 
 
-@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("mode", MODES + FP64_MODES)
 def test_lognormal_zipf_200m_full_size(c2, mode):
     check_unique_full_size(c2, mode, 1)
 

@@ -134,11 +134,27 @@ def test_empty_relations():
     assert ko.numel() == 0 and po.numel() == 0
 
 
-def test_fullsize_sampled():
-    """lognormal-zipf-200M with R shuffled, the benchmark's launch: the
-    total equals the generator's exact hit count (R distinct, 90% hits), and
-    sampled pairs are checked one by one against the oracle's equal_range on
-    the sorted R mapped through the generator's shuffle."""
+@pytest.mark.parametrize("scale", [0.025, 0.2], ids=["5M", "40M"])
+def test_lognormal_zipf_scaled_every_partition_pass(scale):
+    """Element by element against the oracle's sort join at sizes whose
+    partition of R takes the full-size path: 5e6 keys give 8 sub-partitions
+    per segment, 8192 partitions, 13 partition bits (three 6-bit passes over
+    R, S partitioned by the high 12 bits after a shift of 1); 4e7 keys give
+    65536 partitions, 16 bits, three passes and a shift of 4 (full size:
+    2^18 partitions, 18 bits, shift 6)."""
+    w = workloads.shuffled_inner(workloads.c2_lognormal_zipf(scale=scale))
+    got = join_parity(w.R, w.S, w.name)
+    assert len(got) == w.expected_count
+
+
+def test_fullsize_exact():
+    """lognormal-zipf-200M with R shuffled, the benchmark's launch, checked
+    exactly by properties that determine the output: R is duplicate-free,
+    so P holds one pair per hit of S and no s_idx twice; every emitted pair
+    joins equal keys (S[s] == R[r]); s_idx strictly increases; and the count
+    equals the generator's exact hit count (1.8e8).  A pair list with these
+    properties is P.  Sampled pairs are also matched against the oracle's
+    equal_range on the sorted R, mapped through the shuffle."""
     import torch
     base = workloads.c2_lognormal_zipf()
     w = workloads.shuffled_inner(base)
@@ -152,17 +168,18 @@ def test_fullsize_sampled():
     lj.lj_sort_join_async(R, S, out, cnt, ws)
     torch.cuda.synchronize()
     count = int(cnt.item())
-    assert count == w.expected_count
-    # Position of each sorted key in the shuffled R.
-    pos_of = np.empty(n, dtype=np.uint32)
-    order = np.argsort(w.R, kind="stable")
-    pos_of[:] = order.astype(np.uint32)  # pos_of[i] = shuffled position of base.R[i]
+    assert count == w.expected_count == 180_000_000
+    del ws, R, S
+    P = out[:count].cpu().numpy().view(np.uint32)
+    del out
+    s_idx = P[:, 0].astype(np.int64)
+    r_idx = P[:, 1].astype(np.int64)
+    assert np.all(np.diff(s_idx) > 0)
+    assert np.array_equal(w.S[s_idx], w.R[r_idx])
+    # Sampled pairs against the oracle's binary search on the sorted R.
+    pos_of = np.argsort(w.R, kind="stable").astype(np.uint32)  # sorted rank -> position
     rng = np.random.default_rng(11)
-    idx = np.sort(rng.choice(count, 20_000, replace=False))
-    pairs = out[torch.from_numpy(idx).cuda()].cpu().numpy().view(np.uint32).reshape(-1, 2)
-    s_idx = pairs[:, 0].astype(np.int64)
-    first, c = oracle.equal_range(base.R, w.S[s_idx])
+    pick = rng.choice(count, 20_000, replace=False)
+    first, c = oracle.equal_range(base.R, w.S[s_idx[pick]])
     assert np.all(c == 1)
-    assert np.array_equal(pairs[:, 1], pos_of[first.astype(np.int64)])
-    # Pairs are in s order: the sampled s indices are non-decreasing.
-    assert np.all(np.diff(s_idx) >= 0)
+    assert np.array_equal(r_idx[pick], pos_of[first.astype(np.int64)].astype(np.int64))
