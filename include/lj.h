@@ -212,6 +212,31 @@ int lj_probe_join_async(const lj_index* index, const uint64_t* s_keys_dev,
                         hipStream_t stream);
 
 /*
+ * Probe that allocates nothing, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the result and capacity protocol of
+ * lj_probe_join_async, always by the direct probe, with the probe's
+ * workspace (tile and done counters, error flag, one status word per tile)
+ * in a fixed 4 MiB device array that the library holds on every GPU it runs
+ * on until the process ends.  No hipMalloc, hipFree or other allocation is
+ * made; the array is cleared by a kernel at the start of every call.
+ *
+ *   m              0 <= m <= lj_probe_join_noalloc_max_keys() (536,838,144);
+ *                  larger m returns LJ_ERR_TOO_LARGE.
+ *   out_count_dev  device uint64 receiving the total pair count (UINT64_MAX
+ *                  if a kernel hit its internal wait bound).
+ *
+ * All calls on one GPU share that GPU's array: calls that overlap on one
+ * GPU (two streams, or two host threads) race and give wrong results; order
+ * them on one stream.  Errors (host-side checks only): LJ_ERR_ARG,
+ * LJ_ERR_TOO_LARGE, LJ_ERR_DEVICE.
+ */
+uint64_t lj_probe_join_noalloc_max_keys(void);
+int lj_probe_join_noalloc(const lj_index* index, const uint64_t* s_keys_dev, uint64_t m,
+                          lj_pair* out_pairs_dev, uint64_t out_capacity,
+                          uint64_t* out_count_dev, hipStream_t stream);
+
+/*
  * Batched probe of many indexes as one replayable unit.
  *
  * Each descriptor is one independent probe with the semantics and capacity

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblj.so")
 
 SOURCES = ["lj_build.cpp", "lj_kernels.hip", "lj_partition.hip", "lj_sortjoin.hip", "lj_microbench.hip", "lj_api.cpp", "lj_batch.cpp",
-           "lj_server.cpp"]
+           "lj_server.cpp", "lj_noalloc.cpp"]
 HEADERS = ["rmi_eval.h", "lj_internal.h", "lj_device.h", "lj_batch.h", "lj_sortjoin.h", os.path.join("..", "..", "include", "lj.h")]
 
 HIPCC_FLAGS = [

@@ -43,6 +43,7 @@ EXPORTED = (
     "lj_build_gapped_rmi", "lj_build_gapped_rmi_host_only", "lj_gapped_slots_host",
     "lj_build_learned_hash", "lj_build_learned_hash_host_only", "lj_hash_buckets_host",
     "lj_sort_join_workspace_bytes", "lj_sort_join_async", "lj_learned_sort_async",
+    "lj_probe_join_noalloc", "lj_probe_join_noalloc_max_keys",
 )
 GAP_SLOT = 0xFFFFFFFF  # payload of a gap slot in lj_gapped_slots_host
 
@@ -190,6 +191,9 @@ def lib() -> ctypes.CDLL:
         L.lj_sort_join_workspace_bytes.restype = u64
         L.lj_sort_join_async.argtypes = [vp, u64, vp, u64, vp, u64, vp, vp, u64, vp]
         L.lj_learned_sort_async.argtypes = [vp, u64, vp, vp, vp, u64, vp]
+        L.lj_probe_join_noalloc.argtypes = [vp, vp, u64, vp, u64, vp, vp]
+        L.lj_probe_join_noalloc_max_keys.argtypes = []
+        L.lj_probe_join_noalloc_max_keys.restype = u64
         L.lj_strerror.argtypes = [i32]
         L.lj_strerror.restype = ctypes.c_char_p
         for f in ("lj_build_rmi", "lj_build_rmi_host_only", "lj_probe_join",
@@ -199,7 +203,8 @@ def lib() -> ctypes.CDLL:
                   "lj_batch_plan_create", "lj_batch_plan_run", "lj_batch_autotune",
                   "lj_server_create", "lj_server_submit", "lj_server_submit_device",
                   "lj_server_wait",
-                  "lj_server_get_stats", "lj_sort_join_async", "lj_learned_sort_async"):
+                  "lj_server_get_stats", "lj_sort_join_async", "lj_learned_sort_async",
+                  "lj_probe_join_noalloc"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -383,6 +388,23 @@ def lj_probe_join_async(index: Index, s_keys_dev, out_pairs_dev, count_dev, work
                                      _dev_ptr(out_pairs_dev) if cap else None, cap,
                                      _dev_ptr(count_dev), _dev_ptr(workspace_dev), ws_bytes,
                                      _stream_ptr(stream)), "lj_probe_join_async")
+
+
+def lj_probe_join_noalloc(index: Index, s_keys_dev, out_pairs_dev, count_dev,
+                          stream=None) -> None:
+    """Enqueue a direct probe whose workspace is the library's fixed device
+    array (nothing is allocated); count_dev is a device int64 tensor of one
+    element.  Calls on one GPU must not overlap."""
+    m = s_keys_dev.numel()
+    cap = 0 if out_pairs_dev is None else out_pairs_dev.shape[0]
+    _check(lib().lj_probe_join_noalloc(index.handle, _dev_ptr(s_keys_dev) if m else None, m,
+                                       _dev_ptr(out_pairs_dev) if cap else None, cap,
+                                       _dev_ptr(count_dev), _stream_ptr(stream)),
+           "lj_probe_join_noalloc")
+
+
+def lj_probe_join_noalloc_max_keys() -> int:
+    return int(lib().lj_probe_join_noalloc_max_keys())
 
 
 def lj_sort_join_workspace_bytes(n: int, m: int) -> int:
