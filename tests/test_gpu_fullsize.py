@@ -33,6 +33,12 @@ HASH_MODES = [(lj.LJ_LEAF_FP32, "hash", 4), (lj.LJ_LEAF_FP32 | BIN, "hash", 4),
               (lj.LJ_LEAF_FP32 | BIN, "rmi", 0)]
 
 
+def mode_id(mode):
+    flags, kind, spk = mode
+    return (f"{'fp64' if flags & lj.LJ_LEAF_FP64 else 'fp32'}-"
+            f"{'binned' if flags & BIN else 'direct'}-{kind}")
+
+
 def build(w, mode):
     flags, kind, spk = mode
     leaf = "fp64" if flags & lj.LJ_LEAF_FP64 else "fp32"
@@ -92,7 +98,7 @@ def check_unique_full_size(w, mode, seed):
     assert np.array_equal(ri[pos_c][emitted], first[emitted].astype(np.int64))
 
 
-@pytest.mark.parametrize("mode", MODES + FP64_MODES)
+@pytest.mark.parametrize("mode", MODES + FP64_MODES, ids=mode_id)
 def test_lognormal_zipf_200m_full_size(c2, mode):
     check_unique_full_size(c2, mode, 1)
 
@@ -103,12 +109,12 @@ def c6():
     return workloads.c6_seq_holes()
 
 
-@pytest.mark.parametrize("mode", HASH_MODES)
+@pytest.mark.parametrize("mode", HASH_MODES, ids=mode_id)
 def test_seq_holes_200m_full_size(c6, mode):
     check_unique_full_size(c6, mode, 3)
 
 
-@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("mode", MODES, ids=mode_id)
 def test_dup_runs_100m_full_size(c3, mode):
     """1e8 rows of seq_h values repeated U{1..16} times, 1e8 outer keys with
     70% hits: about 6e8 pairs.  Exact by: every pair matches, pairs strictly
