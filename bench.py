@@ -82,45 +82,42 @@ def load_traffic_sort_join(workload: str):
                             kernel_source_hash_sort_join())
 
 
-def load_traffic(workload: str, binned: bool, index: str = "rmi"):
+def probe_summary_path(workload: str, binned: bool, index: str = "rmi",
+                       root: str = "linear") -> str:
+    """Committed rocprofv3 counter summary of one probe form."""
+    kind = (("probe_binned" if binned else "probe") + ("" if index == "rmi" else "_" + index)
+            + ("" if root == "linear" else "_" + root))
+    return os.path.join(ROOT, "profiles", f"{kind}_{workload}_hbm_counters.md")
+
+
+def _summary_value(path: str, key: str):
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals[key])
+    except (KeyError, ValueError):
+        return None
+
+
+def load_traffic(workload: str, binned: bool, index: str = "rmi", root: str = "linear"):
     """HBM bytes per launch of the timed kernel from the committed rocprofv3
     counter summary, or None when absent or taken on a different kernel
     source."""
-    kind = ("probe_binned" if binned else "probe") + ("" if index == "rmi" else "_" + index)
-    path = os.path.join(ROOT, "profiles", f"{kind}_{workload}_hbm_counters.md")
-    if not os.path.exists(path):
-        return None
-    vals = {}
-    for line in open(path):
-        if line.startswith("- ") and ":" in line:
-            k, v = line[2:].split(":", 1)
-            vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel_source_sha256") != kernel_source_hash():
-        return None
-    try:
-        return float(vals["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    return _summary_value(probe_summary_path(workload, binned, index, root),
+                          "traffic_bytes_per_launch")
 
 
-def load_step_traffic(workload: str, binned: bool, index: str = "rmi"):
+def load_step_traffic(workload: str, binned: bool, index: str = "rmi", root: str = "linear"):
     """HBM bytes of a whole probe step (every library kernel) from the same
     counter summary, or None."""
-    kind = ("probe_binned" if binned else "probe") + ("" if index == "rmi" else "_" + index)
-    path = os.path.join(ROOT, "profiles", f"{kind}_{workload}_hbm_counters.md")
-    if not os.path.exists(path):
-        return None
-    vals = {}
-    for line in open(path):
-        if line.startswith("- ") and ":" in line:
-            k, v = line[2:].split(":", 1)
-            vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel_source_sha256") != kernel_source_hash():
-        return None
-    try:
-        return float(vals["step_bytes"])
-    except (KeyError, ValueError):
-        return None
+    return _summary_value(probe_summary_path(workload, binned, index, root), "step_bytes")
 
 
 def make_workload(name: str):
@@ -368,6 +365,11 @@ def bench_sort_join(args) -> None:
     print(json.dumps(res), flush=True)
 
 
+def root_flag(args) -> int:
+    from paper_2111_08824_amd import lj
+    return lj.LJ_ROOT_RADIX if args.root == "radix" else 0
+
+
 def _json_line(res: dict) -> None:
     print(json.dumps(res), flush=True)
 
@@ -391,7 +393,7 @@ def bench_multi_index(args) -> None:
     stream = torch.cuda.current_stream()
     batches, expected, wspaces = [], [], []
     for w in ws:
-        ix = lj.lj_build_rmi(w.R, w.leaves, lj.LJ_LEAF_FP32, stream)
+        ix = lj.lj_build_rmi(w.R, w.leaves, lj.LJ_LEAF_FP32 | root_flag(args), stream)
         s = lj.to_device_keys(w.S)
         out = torch.empty((max(1, len(w.S)), 2), dtype=torch.int32, device="cuda")
         cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -481,7 +483,7 @@ def bench_multi_index(args) -> None:
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "multi-index-64", "indexes": 64,
                    "inner_keys": int(sum(len(w.R) for w in ws)), "outer_keys": int(m_total),
-                   "leaf_model": "fp32", "tuning": tuning.as_dict()},
+                   "leaf_model": "fp32", "root": args.root, "tuning": tuning.as_dict()},
         "plain_per_batch_sync": {"ms_per_step": round(sync_ms, 4),
                                  "probes_per_s": m_total / (sync_ms * 1e-3)},
         "plain_per_batch_async": {"ms_per_step": round(async_ms, 4),
@@ -513,7 +515,7 @@ def bench_serving(args) -> None:
 
     t0 = time.perf_counter()
     ws = workloads.resident_indexes()
-    ixs = [lj.lj_build_rmi(w.R, w.leaves, lj.LJ_LEAF_FP32) for w in ws]
+    ixs = [lj.lj_build_rmi(w.R, w.leaves, lj.LJ_LEAF_FP32 | root_flag(args)) for w in ws]
     print(f"[bench] 8 resident indexes ready ({time.perf_counter() - t0:.1f} s)",
           file=sys.stderr, flush=True)
     rng = np.random.default_rng(7)
@@ -663,7 +665,7 @@ def bench_serving(args) -> None:
         "ms_per_step": round(w_served * 1e3 / len(sat_reqs), 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "serving-8x50M", "indexes": 8, "inner_keys_each": 50_000_000,
-                   "leaf_model": "fp32",
+                   "leaf_model": "fp32", "root": args.root,
                    "request_keys": "log-uniform 256..4194304", "requests_per_load": nreq,
                    "request_buffers": args.request_buffers, "server": best},
         "saturation": {**{f"{n}_probes_per_s": keys_sat / sat[n][0] for n, _ in configs},
@@ -747,7 +749,7 @@ def bench_inlj(args) -> None:
     w = make_workload(args.workload)
     print(f"[bench] workload {w.name}: n={len(w.R)} m={len(w.S)} leaves={w.leaves} "
           f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
-    flags = lj.LJ_LEAF_FP32 if args.leaf == "fp32" else lj.LJ_LEAF_FP64
+    flags = (lj.LJ_LEAF_FP32 if args.leaf == "fp32" else lj.LJ_LEAF_FP64) | root_flag(args)
     if args.search == "exponential":
         flags |= lj.LJ_SEARCH_EXPONENTIAL
     binned = args.probe == "binned"
@@ -828,8 +830,9 @@ def bench_inlj(args) -> None:
     # the default slots per key.
     summary_ok = (args.leaf == "fp32" and args.search == "binary"
                   and (args.index == "rmi" or args.slots_per_key == 4))
-    traffic = load_traffic(w.name, binned, args.index) if summary_ok else None
-    step_traffic = load_step_traffic(w.name, binned, args.index) if summary_ok else None
+    traffic = load_traffic(w.name, binned, args.index, args.root) if summary_ok else None
+    step_traffic = (load_step_traffic(w.name, binned, args.index, args.root) if summary_ok
+                    else None)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
@@ -884,7 +887,7 @@ def bench_inlj(args) -> None:
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": w.name, "n": len(w.R), "m": m, "leaves": w.leaves,
-                   "leaf_model": args.leaf,
+                   "leaf_model": args.leaf, "root": args.root,
                    "search": ("gapped-exponential" if gapped else "bucket-chain" if hashed
                               else args.search),
                    "probe": args.probe,
@@ -908,6 +911,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lognormal-zipf-200M")
     ap.add_argument("--leaf", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--root", choices=["linear", "radix"], default="linear",
+                    help="root model: one least-squares line, or a piecewise-linear CDF "
+                         "over a radix table of the key")
     ap.add_argument("--search", choices=["binary", "exponential"], default="binary",
                     help="last-mile search inside the error bounds")
     ap.add_argument("--probe", choices=["direct", "binned"], default="binned",

@@ -65,12 +65,24 @@ enum {
     LJ_SEARCH_EXPONENTIAL = 4u, /* last-mile search gallops out from the prediction
                                    (steps 8, 16, 32, ...) inside the error bounds, then
                                    bisects; without it, binary search over the bounds */
-    LJ_PROBE_BINNED = 8u        /* probes put S in key order first: 4096 equi-depth key
+    LJ_PROBE_BINNED = 8u,       /* probes put S in key order first: 4096 equi-depth key
                                    ranges of R, two stable partition passes, searches
                                    in that order with each XCD on its own ranges, results
                                    put back in S order before emission (the locality of
                                    buffering requests per node, Section III-B).  Same
                                    output; about 28 more workspace bytes per outer key */
+    LJ_ROOT_RADIX = 16u         /* root model = piecewise-linear CDF over a radix table
+                                   of the key instead of one least-squares line (the
+                                   radix-table idea of RadixSpline, Section II-D; the
+                                   paper's RMIs are tuned over root model types).  The
+                                   key's offset from R[0] picks one of 3776 buckets by
+                                   its exponent and next 6 bits; the table holds the
+                                   leaf coordinate leaves * rank / n of every bucket
+                                   edge and the root interpolates inside the bucket in
+                                   integer arithmetic.  Leaves then hold about n / leaves
+                                   keys each on skewed data too (a line puts most keys
+                                   of a heavy-tailed R into a few leaves).  Same output;
+                                   15 KB more per index */
 };
 
 /*

@@ -51,7 +51,7 @@ int check_device(const lj_index* idx) {
 int validate_build(const uint64_t* r, uint64_t n, uint32_t leaves, uint32_t flags) {
     if (n > 0 && !r) return LJ_ERR_ARG;
     if (leaves == 0) return LJ_ERR_ARG;
-    if ((flags & ~15u) || ((flags & 3u) != LJ_LEAF_FP32 && (flags & 3u) != LJ_LEAF_FP64))
+    if ((flags & ~31u) || ((flags & 3u) != LJ_LEAF_FP32 && (flags & 3u) != LJ_LEAF_FP64))
         return LJ_ERR_ARG;
     if (n >= kMaxN || leaves > kMaxLeaves) return LJ_ERR_TOO_LARGE;
     for (uint64_t i = 1; i < n; ++i)
@@ -172,18 +172,21 @@ int build_device(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves, uint3
     const uint64_t hbytes = idx->buckets.size() * sizeof(lj::HBucket);
     const uint64_t nrs = (n + lj::kLineKeys - 1) / lj::kLineKeys;
     const uint64_t rsbytes = nrs * sizeof(uint64_t);
+    const uint64_t tbytes = idx->root_tab.size() * sizeof(uint32_t);
     if (hipMalloc((void**)&idx->r_dev, rbytes) != hipSuccess ||
         hipMalloc(&idx->leaf_dev, lbytes) != hipSuccess ||
         (fbytes && hipMalloc((void**)&idx->fences_dev, fbytes) != hipSuccess) ||
         (bbytes && hipMalloc((void**)&idx->bucket_lo_dev, bbytes) != hipSuccess) ||
         (sbytes && hipMalloc((void**)&idx->slots_dev, sbytes) != hipSuccess) ||
         (hbytes && hipMalloc((void**)&idx->buckets_dev, hbytes) != hipSuccess) ||
-        (rsbytes && hipMalloc((void**)&idx->rs_dev, rsbytes) != hipSuccess)) {
+        (rsbytes && hipMalloc((void**)&idx->rs_dev, rsbytes) != hipSuccess) ||
+        (tbytes && hipMalloc((void**)&idx->root_tab_dev, tbytes) != hipSuccess)) {
         (void)hipGetLastError();
         lj_free_index(idx);
         return LJ_ERR_OOM;
     }
-    idx->device_bytes = rbytes + lbytes + fbytes + bbytes + sbytes + hbytes + rsbytes;
+    idx->device_bytes = rbytes + lbytes + fbytes + bbytes + sbytes + hbytes + rsbytes + tbytes;
+    idx->root.tab_dev = idx->root_tab_dev;
     hipError_t e = hipSuccess;
     if (n) e = hipMemcpyAsync(idx->r_dev, r_keys_host, n * sizeof(uint64_t),
                               hipMemcpyHostToDevice, stream);
@@ -201,6 +204,9 @@ int build_device(const uint64_t* r_keys_host, uint64_t n, uint32_t leaves, uint3
     if (e == hipSuccess && hbytes)
         e = hipMemcpyAsync(idx->buckets_dev, idx->buckets.data(), hbytes, hipMemcpyHostToDevice,
                            stream);
+    if (e == hipSuccess && tbytes)
+        e = hipMemcpyAsync(idx->root_tab_dev, idx->root_tab.data(), tbytes,
+                           hipMemcpyHostToDevice, stream);
     if (e == hipSuccess && rsbytes)
         e = lj::launch_line_samples(idx->r_dev, n, idx->rs_dev, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -227,6 +233,7 @@ void lj_free_index(lj_index* idx) {
     if (idx->slots_dev) (void)hipFree(idx->slots_dev);
     if (idx->buckets_dev) (void)hipFree(idx->buckets_dev);
     if (idx->rs_dev) (void)hipFree(idx->rs_dev);
+    if (idx->root_tab_dev) (void)hipFree(idx->root_tab_dev);
     delete idx;
 }
 

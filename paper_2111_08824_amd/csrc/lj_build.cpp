@@ -141,10 +141,40 @@ int fit_rmi(const uint64_t* r, uint64_t n, uint32_t L, uint32_t flags, lj_index*
     idx->leaves = L;
     idx->flags = flags;
 
-    // Root: least squares from (key - R[0]) to the leaf coordinate i*L/n.
     RootModel rm{};
     rm.leaves = L;
-    if (n > 0) {
+    if (flags & LJ_ROOT_RADIX) {
+        // Radix root: the leaf coordinate L * rank / n of every bucket's
+        // lower edge, rank = keys of R below it (fixed point with as many
+        // fraction bits as keep L << frac_bits below 2^31).
+        rm.kind = kRootRadix;
+        rm.kmin = n ? r[0] : 0;
+        uint32_t lg = 0;
+        while ((1ull << lg) < L) ++lg;
+        rm.frac_bits = 31 - lg;
+        const uint64_t full = (uint64_t)L << rm.frac_bits;
+        std::vector<uint32_t>& tab = idx->root_tab;
+        tab.assign(kRootBuckets + 1, (uint32_t)full);
+        for (uint32_t b = 0; b < kRootBuckets && n > 0; ++b) {
+            // Lower edge of bucket b as an offset from kmin.
+            unsigned __int128 edge;
+            if (b < (1u << kRootSubBits)) {
+                edge = b;
+            } else {
+                const uint32_t e = (b >> kRootSubBits) + kRootSubBits - 1;
+                const uint32_t sub = b & ((1u << kRootSubBits) - 1);
+                edge = (unsigned __int128)((1u << kRootSubBits) + sub) << (e - kRootSubBits);
+            }
+            const unsigned __int128 key = (unsigned __int128)rm.kmin + edge;
+            uint64_t rank = n;
+            if (key <= (unsigned __int128)~0ull)
+                rank = (uint64_t)(std::lower_bound(r, r + n, (uint64_t)key) - r);
+            tab[b] = (uint32_t)(((unsigned __int128)rank * full) / n);
+        }
+        rm.tab_host = tab.data();
+    } else if (n > 0) {
+        // Linear root: least squares from (key - R[0]) to the leaf
+        // coordinate i*L/n.
         rm.kmin = r[0];
         const double scale = (double)L / (double)n;
         Fit f = ols(n, [&](uint64_t i) { return u64_to_f64(r[i] - r[0]); },

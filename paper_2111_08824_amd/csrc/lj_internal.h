@@ -46,6 +46,8 @@ struct lj_index {
     int device = -1;
 
     lj::RootModel root{};
+    std::vector<uint32_t> root_tab;      // radix root: host copy (root.tab_host)
+    uint32_t* root_tab_dev = nullptr;    // radix root: device copy (root.tab_dev)
     std::vector<lj::LeafF32> leaf32;  // host copy (LJ_LEAF_FP32)
     std::vector<lj::LeafF64> leaf64;  // host copy (LJ_LEAF_FP64)
 

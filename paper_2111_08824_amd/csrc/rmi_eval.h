@@ -19,13 +19,35 @@
 
 namespace lj {
 
-// Root model: leaf = clamp(floor(a0 + b0 * (x - kmin)), 0, L - 1).
+// Root model, one of two kinds:
+//   linear:  leaf = clamp(floor(a0 + b0 * (x - kmin)), 0, L - 1);
+//   radix:   a piecewise-linear CDF over a radix table of the key.  The
+//            offset x' = x - kmin (0 below kmin) falls in one of kRootBuckets
+//            buckets of a float-like code (the exponent of x' and its next
+//            kRootSubBits bits; values below 2^kRootSubBits are their own
+//            buckets), so bucket widths are powers of two that grow with
+//            x'.  tab[b] holds the leaf coordinate (fixed point, frac_bits
+//            fraction bits) of bucket b's lower edge: leaves * rank / n,
+//            with rank the number of keys of R below it.  Inside a bucket
+//            the coordinate is interpolated linearly, in integers only:
+//            tab[b] + ((tab[b+1] - tab[b]) * r) >> w, with r the top (at
+//            most 32) bits of x' below the bucket's leading bits and 2^w
+//            their range.  Non-decreasing in x, exact on host and device.
+// The table is read through tab_dev in device code and tab_host on the host.
+constexpr uint32_t kRootLinear = 0;
+constexpr uint32_t kRootRadix = 1;
+constexpr uint32_t kRootSubBits = 6;
+constexpr uint32_t kRootBuckets = (64 - kRootSubBits + 1) << kRootSubBits;  // 3776
 struct RootModel {
     double a0;
     double b0;
     uint64_t kmin;
     uint32_t leaves;
+    uint32_t kind;       // kRootLinear or kRootRadix
+    uint32_t frac_bits;  // radix: fraction bits of the table's coordinates
     uint32_t pad;
+    const uint32_t* tab_host;  // radix: kRootBuckets + 1 coordinates
+    const uint32_t* tab_dev;
 };
 
 // Leaf record, FP32 model (32 bytes).  Positions are relative to pos0, the
@@ -106,8 +128,47 @@ __host__ __device__ inline int32_t f64_to_i32_sat(double d) {
     return (int32_t)d;
 }
 
-// Root routing (FP64): non-decreasing in x because b0 >= 0.
+// Bucket of the radix root for offset xp, with the offset's bits below the
+// bucket's leading bits, cut to their top 32 (*rem), and the number of
+// those bits kept (*w; the bucket spans 2^w values of *rem).
+__host__ __device__ inline uint32_t root_bucket(uint64_t xp, uint64_t* rem, uint32_t* w) {
+    if (xp < (1ull << kRootSubBits)) {
+        *rem = 0;
+        *w = 0;
+        return (uint32_t)xp;
+    }
+    const uint32_t e = 63u - (uint32_t)clz64(xp);  // >= kRootSubBits
+    const uint32_t low = e - kRootSubBits;          // bits below the bucket's leading bits
+    const uint32_t sub = (uint32_t)(xp >> low) & ((1u << kRootSubBits) - 1u);
+    const uint64_t r = low ? xp & ((1ull << low) - 1ull) : 0ull;
+    const uint32_t cut = low > 32u ? low - 32u : 0u;
+    *rem = r >> cut;
+    *w = low - cut;
+    return ((e - kRootSubBits + 1u) << kRootSubBits) | sub;
+}
+
+// Radix root with the table at `tab` (global or LDS copy).
+__host__ __device__ inline uint32_t route_radix(const RootModel& rm, const uint32_t* tab,
+                                                uint64_t x) {
+    uint64_t rem;
+    uint32_t w;
+    const uint32_t b = root_bucket(sat_sub(x, rm.kmin), &rem, &w);
+    const uint32_t t0 = tab[b], t1 = tab[b + 1];
+    const uint64_t coord = (uint64_t)t0 + (((uint64_t)(t1 - t0) * rem) >> w);
+    const uint64_t leaf = coord >> rm.frac_bits;
+    return leaf < rm.leaves ? (uint32_t)leaf : rm.leaves - 1;
+}
+
+// Root routing: non-decreasing in x (linear: b0 >= 0, FP64; radix: the
+// table is non-decreasing).
 __host__ __device__ inline uint32_t route(const RootModel& rm, uint64_t x) {
+    if (rm.kind == kRootRadix) {
+#ifdef __HIP_DEVICE_COMPILE__
+        return route_radix(rm, rm.tab_dev, x);
+#else
+        return route_radix(rm, rm.tab_host, x);
+#endif
+    }
     double r = fma(rm.b0, u64_to_f64(sat_sub(x, rm.kmin)), rm.a0);
     if (!(r > 0.0)) return 0;
     if (r >= (double)rm.leaves) return rm.leaves - 1;

@@ -31,6 +31,7 @@ LJ_LEAF_FP32 = 1
 LJ_LEAF_FP64 = 2
 LJ_SEARCH_EXPONENTIAL = 4
 LJ_PROBE_BINNED = 8
+LJ_ROOT_RADIX = 16
 
 EXPORTED = (
     "lj_build_rmi", "lj_free_index", "lj_probe_join", "lj_probe_workspace_bytes",

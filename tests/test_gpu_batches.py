@@ -21,6 +21,8 @@ def _mixed_batches(seed=7):
     items = []
     for i, w in enumerate(ws):
         flags = lj.LJ_LEAF_FP64 if i % 3 == 1 else lj.LJ_LEAF_FP32
+        if i % 4 == 2:
+            flags |= lj.LJ_ROOT_RADIX
         S = w.S if i != 4 else w.S[:0]  # one empty batch
         ix = lj.lj_build_rmi(w.R, w.leaves, flags)
         cap = max(1, len(S) * int(ix.stats.max_mult))

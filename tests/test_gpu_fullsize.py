@@ -29,14 +29,23 @@ MODES = [(lj.LJ_LEAF_FP32, "rmi", 0), (lj.LJ_LEAF_FP32 | BIN, "rmi", 0),
 # The FP64 leaf model of the same index: the other half of the FP32 / FP64
 # comparison at full size (48-byte leaf records, f64 windows).
 FP64_MODES = [(lj.LJ_LEAF_FP64, "rmi", 0), (lj.LJ_LEAF_FP64 | BIN, "rmi", 0)]
+# The radix root (piecewise-linear CDF over a radix table) on the same
+# relations: other leaves, other windows, the same pairs.
+RADIX = lj.LJ_ROOT_RADIX
+RADIX_MODES = [(lj.LJ_LEAF_FP32 | RADIX, "rmi", 0), (lj.LJ_LEAF_FP32 | RADIX | BIN, "rmi", 0),
+               (lj.LJ_LEAF_FP64 | RADIX, "rmi", 0), (lj.LJ_LEAF_FP32 | RADIX, "gapped", 4)]
 HASH_MODES = [(lj.LJ_LEAF_FP32, "hash", 4), (lj.LJ_LEAF_FP32 | BIN, "hash", 4),
-              (lj.LJ_LEAF_FP32 | BIN, "rmi", 0)]
+              (lj.LJ_LEAF_FP32 | BIN, "rmi", 0), (lj.LJ_LEAF_FP32 | RADIX, "hash", 4),
+              (lj.LJ_LEAF_FP32 | RADIX, "rmi", 0)]
+DUP_MODES = MODES + [(lj.LJ_LEAF_FP32 | RADIX, "rmi", 0),
+                     (lj.LJ_LEAF_FP32 | RADIX | BIN, "rmi", 0)]
 
 
 def mode_id(mode):
     flags, kind, spk = mode
     return (f"{'fp64' if flags & lj.LJ_LEAF_FP64 else 'fp32'}-"
-            f"{'binned' if flags & BIN else 'direct'}-{kind}")
+            f"{'binned' if flags & BIN else 'direct'}-{kind}"
+            f"{'-radix' if flags & RADIX else ''}")
 
 
 def build(w, mode):
@@ -98,7 +107,7 @@ def check_unique_full_size(w, mode, seed):
     assert np.array_equal(ri[pos_c][emitted], first[emitted].astype(np.int64))
 
 
-@pytest.mark.parametrize("mode", MODES + FP64_MODES, ids=mode_id)
+@pytest.mark.parametrize("mode", MODES + FP64_MODES + RADIX_MODES, ids=mode_id)
 def test_lognormal_zipf_200m_full_size(c2, mode):
     check_unique_full_size(c2, mode, 1)
 
@@ -114,7 +123,7 @@ def test_seq_holes_200m_full_size(c6, mode):
     check_unique_full_size(c6, mode, 3)
 
 
-@pytest.mark.parametrize("mode", MODES, ids=mode_id)
+@pytest.mark.parametrize("mode", DUP_MODES, ids=mode_id)
 def test_dup_runs_100m_full_size(c3, mode):
     """1e8 rows of seq_h values repeated U{1..16} times, 1e8 outer keys with
     70% hits: about 6e8 pairs.  Exact by: every pair matches, pairs strictly

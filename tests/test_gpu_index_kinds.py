@@ -17,7 +17,8 @@ pytestmark = pytest.mark.gpu
 
 U64MAX = 2**64 - 1
 BIN = lj.LJ_PROBE_BINNED
-FLAGS = [lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP64, lj.LJ_LEAF_FP32 | BIN, lj.LJ_LEAF_FP64 | BIN]
+FLAGS = [lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP64, lj.LJ_LEAF_FP32 | BIN, lj.LJ_LEAF_FP64 | BIN,
+         lj.LJ_LEAF_FP32 | lj.LJ_ROOT_RADIX, lj.LJ_LEAF_FP32 | lj.LJ_ROOT_RADIX | BIN]
 KINDS = ["gapped", "hash"]
 BUILD = {"gapped": lj.lj_build_gapped_rmi, "hash": lj.lj_build_learned_hash}
 BUILD_HOST = {"gapped": lj.lj_build_gapped_rmi_host_only,

@@ -18,8 +18,11 @@ U64MAX = 2**64 - 1
 FLAGS = [lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP64]
 EXP = lj.LJ_SEARCH_EXPONENTIAL
 BIN = lj.LJ_PROBE_BINNED
+RADIX = lj.LJ_ROOT_RADIX
 ALL_FLAGS = FLAGS + [lj.LJ_LEAF_FP32 | EXP, lj.LJ_LEAF_FP64 | EXP, lj.LJ_LEAF_FP32 | BIN,
-                     lj.LJ_LEAF_FP64 | BIN, lj.LJ_LEAF_FP32 | EXP | BIN]
+                     lj.LJ_LEAF_FP64 | BIN, lj.LJ_LEAF_FP32 | EXP | BIN,
+                     lj.LJ_LEAF_FP32 | RADIX, lj.LJ_LEAF_FP64 | RADIX,
+                     lj.LJ_LEAF_FP32 | RADIX | BIN, lj.LJ_LEAF_FP32 | RADIX | EXP]
 
 
 def gpu_join(R, S, leaves, flags, capacity=None):
@@ -69,11 +72,24 @@ def test_ragged_tile_tails(m, search):
 
 
 @pytest.mark.parametrize("leaves", [1, 2, 1000, 200_003])
-@pytest.mark.parametrize("search", [0, EXP, BIN])
+@pytest.mark.parametrize("search", [0, EXP, BIN, RADIX, RADIX | BIN])
 def test_leaf_counts(leaves, search):
     R = workloads.gen.lognormal_unique(50_000, 2.0, 5)
     S = workloads.gen.probe_mix(R, 60_000, 0.5, 6, miss_hi=2**63)
     assert_parity(R, S, leaves, lj.LJ_LEAF_FP32 | search, f"leaves={leaves}")
+
+
+@pytest.mark.parametrize("flags", [lj.LJ_LEAF_FP32 | RADIX, lj.LJ_LEAF_FP32 | RADIX | BIN])
+def test_radix_root_small_and_high_keys(flags):
+    # Offsets from R[0] below 64 (their own root buckets), keys near 2^64
+    # (the last buckets), outer keys below R[0] and above R[n-1].
+    R = np.concatenate([np.arange(10, 90, dtype=np.uint64),
+                        np.uint64(2**64 - 2**30) + np.arange(0, 3000, 7, dtype=np.uint64),
+                        np.array([U64MAX], dtype=np.uint64)])
+    S = np.concatenate([np.arange(0, 100, dtype=np.uint64), R[::3],
+                        np.array([U64MAX, U64MAX - 1, 2**63], dtype=np.uint64)])
+    for leaves in (1, 5, 64, 1000):
+        assert_parity(R, S, leaves, flags, f"radix root small/high keys, leaves={leaves}")
 
 
 def test_heavy_duplicates_load_balanced_emission():
@@ -185,7 +201,7 @@ def test_async_matches_sync_and_checks_workspace(binned):
 def test_device_windows_equal_host_windows():
     import torch
     for w in (workloads.c1_uniform(scale=0.1), workloads.c2_lognormal_zipf(scale=0.002)):
-        for flags in FLAGS:
+        for flags in FLAGS + [lj.LJ_LEAF_FP32 | RADIX, lj.LJ_LEAF_FP64 | RADIX]:
             ix = lj.lj_build_rmi(w.R, w.leaves, flags)
             keys = np.concatenate([w.R, w.S])
             leaf_h, pred_h, lo_h, hi_h = lj.lj_predict_windows_host(ix, keys)
@@ -211,7 +227,7 @@ def test_windows_around_line_boundaries(n):
     R = np.arange(0, 3 * n, 3, dtype=np.uint64) + np.uint64(5)
     S = np.arange(0, 3 * n + 9, dtype=np.uint64)
     for leaves in (1, max(1, n // 4)):
-        for flags in FLAGS + [lj.LJ_LEAF_FP32 | BIN]:
+        for flags in FLAGS + [lj.LJ_LEAF_FP32 | BIN, lj.LJ_LEAF_FP32 | RADIX]:
             assert_parity(R, S, leaves, flags, f"line boundaries n={n}")
     D = np.repeat(R, 3)  # runs of three equal keys across line ends
     assert_parity(D, S, 1, lj.LJ_LEAF_FP32, f"line boundaries dup n={n}")

@@ -17,7 +17,8 @@ pytestmark = pytest.mark.gpu
 def _indexes():
     ws = [workloads.c1_uniform(scale=0.2), workloads.c3_dup_runs(scale=0.002),
           workloads.c2_lognormal_zipf(scale=0.001)]
-    ixs = [lj.lj_build_rmi(w.R, w.leaves, lj.LJ_LEAF_FP32 if i != 1 else lj.LJ_LEAF_FP64)
+    ixs = [lj.lj_build_rmi(w.R, w.leaves, (lj.LJ_LEAF_FP32 if i != 1 else lj.LJ_LEAF_FP64)
+                           | (lj.LJ_ROOT_RADIX if i == 2 else 0))
            for i, w in enumerate(ws)]
     return ws, ixs
 

@@ -58,7 +58,8 @@ def test_argument_errors():
     assert _build_status(R, flags=lj.LJ_SEARCH_EXPONENTIAL) == lj.LJ_ERR_ARG
     assert _build_status(R, flags=lj.LJ_LEAF_FP64 | lj.LJ_SEARCH_EXPONENTIAL) == lj.LJ_OK
     assert _build_status(R, flags=lj.LJ_LEAF_FP32 | lj.LJ_PROBE_BINNED) == lj.LJ_OK
-    assert _build_status(R, flags=lj.LJ_LEAF_FP32 | 16) == lj.LJ_ERR_ARG
+    assert _build_status(R, flags=lj.LJ_LEAF_FP32 | lj.LJ_ROOT_RADIX) == lj.LJ_OK
+    assert _build_status(R, flags=lj.LJ_LEAF_FP32 | 32) == lj.LJ_ERR_ARG
     assert _build_status(R, leaves=2**26 + 1) == lj.LJ_ERR_TOO_LARGE
     assert _build_status(R, n=2**31) == lj.LJ_ERR_TOO_LARGE  # checked before reading R
     h = ctypes.c_void_p()
@@ -103,7 +104,9 @@ def windows_hold(R, leaves, flags):
     return ix, lo, hi, bool(np.all((lo <= i) & (i <= hi)))
 
 
-@pytest.mark.parametrize("flags", [lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP64])
+@pytest.mark.parametrize("flags", [lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP64,
+                                   lj.LJ_LEAF_FP32 | lj.LJ_ROOT_RADIX,
+                                   lj.LJ_LEAF_FP64 | lj.LJ_ROOT_RADIX])
 @pytest.mark.parametrize("make", [
     lambda: workloads.c1_uniform().R,
     lambda: workloads.c2_lognormal_zipf(scale=0.005).R,
@@ -157,9 +160,17 @@ def test_empty_relation_and_extreme_keys():
     assert np.all(pred == -1)
     assert np.all(lo > hi)  # empty windows
     R = np.array([0, 1, 2**63, U64MAX - 1, U64MAX], dtype=np.uint64)
-    for flags in (lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP64):
+    for flags in (lj.LJ_LEAF_FP32, lj.LJ_LEAF_FP64, lj.LJ_LEAF_FP32 | lj.LJ_ROOT_RADIX):
         _, _, _, ok = windows_hold(R, 3, flags)
         assert ok
+    # Radix root: R starting high (offsets from R[0] are small), keys up to
+    # 2^64 - 1 (the last buckets), keys below R[0] and above R[n-1].
+    R = np.array([2**64 - 2**20 + 3 * i for i in range(1000)] + [U64MAX], dtype=np.uint64)
+    ix, _, _, ok = windows_hold(R, 16, lj.LJ_LEAF_FP32 | lj.LJ_ROOT_RADIX)
+    assert ok
+    leaf, _, _, _ = lj.lj_predict_windows_host(
+        ix, np.array([0, 2**63, int(R[0]) - 1, U64MAX], dtype=np.uint64))
+    assert list(leaf) == [0, 0, 0, 15]
 
 
 def test_fp32_and_fp64_bounds_are_close():
@@ -221,3 +232,33 @@ def test_sort_join_workspace_and_argument_checks():
     assert L.lj_learned_sort_async(fake, 10, fake, fake, fake, ws(10, 0) - 1, None) \
         == lj.LJ_ERR_WORKSPACE
     assert L.lj_learned_sort_async(None, 0, None, None, None, 0, None) == lj.LJ_OK
+
+
+@pytest.mark.parametrize("make", [
+    lambda: workloads.c2_lognormal_zipf(scale=0.01).R,
+    lambda: workloads.c1_uniform().R,
+    lambda: workloads.gen.seq_holes(1_000_000, 3),
+    lambda: workloads.c3_dup_runs(scale=0.01).R,
+])
+def test_radix_root_balances_leaves(make):
+    # The radix root interpolates the CDF of R between bucket edges that are
+    # at most 1/64 of an octave apart, so leaf l gets about the keys of ranks
+    # [l n / L, (l + 1) n / L): every key of R routes within a few leaves of
+    # i L / n (runs of equal keys route together, hence the slack of the
+    # longest run), routing is non-decreasing, and no leaf holds more than a
+    # small multiple of n / L keys.  The linear root on the lognormal R puts
+    # most keys into a handful of leaves.
+    R = make()
+    n = len(R)
+    L = workloads.default_leaves(n)
+    ix = lj.lj_build_rmi_host_only(R, L, lj.LJ_LEAF_FP32 | lj.LJ_ROOT_RADIX)
+    leaf, _, _, _ = lj.lj_predict_windows_host(ix, R)
+    leaf = leaf.astype(np.int64)
+    assert np.all(np.diff(leaf) >= 0)
+    ideal = (np.arange(n, dtype=np.int64) * L) // n
+    run = int(ix.stats.max_mult)
+    assert np.all(np.abs(leaf - ideal) <= 0.02 * L + run * L / n + 2)
+    cnt = np.bincount(leaf, minlength=L)
+    assert cnt.max() <= 3 * n / L + run
+    lin = lj.lj_build_rmi_host_only(R, L, lj.LJ_LEAF_FP32)
+    assert ix.stats.max_leaf_keys <= lin.stats.max_leaf_keys
