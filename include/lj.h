@@ -281,7 +281,11 @@ typedef struct {
  * `binned_min_keys`: batches of at least this many outer keys use the
  * binned probe (LJ_PROBE_BINNED) and smaller ones the direct probe; 0 keeps
  * each index's own choice, UINT64_MAX probes every batch directly.
- * `measured_ms` is filled by lj_batch_autotune.
+ * `fused` = 1: all batches probed directly on plain RMIs (binary search)
+ * run in one kernel per leaf arithmetic and duplicate class (usually one
+ * launch for the whole plan): the tiles of every batch share one tile-id
+ * queue, each tile with its own batch's keys per lane (at most 16); 0: one
+ * kernel per batch.  `measured_ms` is filled by lj_batch_autotune.
  */
 typedef struct {
     uint32_t keys_per_lane[4];
@@ -289,6 +293,7 @@ typedef struct {
     uint32_t use_graph;
     uint64_t binned_min_keys;
     float measured_ms;
+    uint32_t fused;
 } lj_batch_tuning;
 
 typedef struct lj_batch_plan lj_batch_plan;
@@ -336,13 +341,16 @@ int lj_batch_autotune(const lj_batch_desc* descs, uint32_t k, hipStream_t stream
  * requests in arrival order while the head request's device footprint
  * (keys + output + workspace) fits the memory budget left, forms a batch as
  * soon as one of `slots` streams is free (so requests that arrive while
- * others run join the next batch), and enqueues, request after request,
- * the key copy, the fused probe and the count copy on that stream; batches
- * on different streams overlap on the device and on the copy engines.  A
- * completion thread per stream returns each request as soon as its own
- * work is done (pairs copied back on a second stream), frees its memory and
- * wakes its waiter.  Device memory for requests comes from one
- * arena of `budget_bytes` allocated at creation.
+ * others run join the next batch), and enqueues the batch on that stream:
+ * the key copies, then (with `fused`) one kernel per kernel group for all
+ * requests probed directly on plain RMIs, which writes each
+ * request's count straight into pinned host memory, then every other
+ * request's probe and count copy; batches on different streams overlap on
+ * the device and on the copy engines.  A completion thread per stream
+ * returns each request as soon as its work is done (pairs copied back on a
+ * second stream), frees its memory and wakes its waiter.  Device memory
+ * for requests comes from one arena of `budget_bytes` allocated at
+ * creation.
  */
 typedef struct {
     uint64_t budget_bytes;        /* device memory for request buffers (> 0) */
@@ -354,6 +362,10 @@ typedef struct {
     uint64_t binned_min_keys;     /* requests of at least this many keys use the binned
                                      probe, smaller ones the direct probe; 0 keeps each
                                      index's own choice (LJ_PROBE_BINNED) */
+    uint32_t fused;               /* 1: a batch's direct probes on plain RMIs run in one
+                                     fused launch (see lj_batch_tuning); 0: one probe
+                                     kernel and count copy per request */
+    uint32_t pad;
 } lj_server_config;
 
 typedef struct lj_server lj_server;
@@ -377,7 +389,7 @@ typedef struct {
 } lj_server_stats;
 
 /* Fill *config with defaults for a budget: 8 slots, 16 requests and 2^22
- * keys per batch, keys per lane 4/8/16/24, binned_min_keys 0. */
+ * keys per batch, keys per lane 4/8/16/24, binned_min_keys 0, fused 1. */
 void lj_server_default_config(lj_server_config* config, uint64_t budget_bytes);
 
 /*

@@ -11,13 +11,28 @@
 
 #include "lj_batch.h"
 
+// Batches probed directly on plain RMIs with one leaf arithmetic and
+// duplicate class, run by one fused launch: their jobs (device table in the
+// plan's workspace), tiles and branch.
+struct FusedGroup {
+    int group = 0;
+    uint64_t jobs_off = 0;  // FusedJob table
+    uint64_t hdr_off = 0;   // launch header
+    uint32_t njobs = 0;
+    uint32_t tiles = 0;
+    uint64_t keys = 0;
+    uint32_t branch = 0;
+};
+
 struct lj_batch_plan {
     int device = -1;
     std::vector<lj_batch_desc> descs;
     std::vector<uint64_t> ws_off;    // per batch workspace offset
     std::vector<uint32_t> kpl;       // per batch keys per lane
     std::vector<int> mode;           // per batch probe form (see uses_binned)
+    std::vector<int> fused;          // per batch fused group slot, or -1
     std::vector<uint32_t> branch;    // per batch branch
+    std::vector<FusedGroup> groups;
     void* ws = nullptr;
     uint32_t branches = 1;
     std::vector<hipStream_t> streams;  // one per branch
@@ -54,12 +69,14 @@ void default_tuning(lj_batch_tuning* t) {
     t->use_graph = 1;
     t->binned_min_keys = 0;
     t->measured_ms = 0.f;
+    t->fused = 1;
 }
 
 int validate_tuning(const lj_batch_tuning& t) {
     for (int c = 0; c < 4; ++c)
         if (!kpl_allowed(t.keys_per_lane[c])) return LJ_ERR_ARG;
     if (t.branches < 1 || t.branches > kMaxBranches) return LJ_ERR_ARG;
+    if (t.fused > 1) return LJ_ERR_ARG;
     return LJ_OK;
 }
 
@@ -96,22 +113,35 @@ namespace {
 
 // Enqueue every batch of the plan, forked from `stream` over the branch
 // streams and joined back into it.
+hipError_t enqueue_fused(lj_batch_plan* p, const FusedGroup& g, hipStream_t st) {
+    char* w = (char*)p->ws;
+    return lj::launch_probe_fused((const lj::FusedJob*)(w + g.jobs_off), g.njobs, g.tiles,
+                                  g.group, (uint32_t*)(w + g.hdr_off), st);
+}
+
 hipError_t enqueue_plan(lj_batch_plan* p, hipStream_t stream) {
     const size_t k = p->descs.size();
     if (p->branches == 1) {
-        for (size_t b = 0; b < k; ++b) {
-            hipError_t e = lj::enqueue_one(p->descs[b], (char*)p->ws + p->ws_off[b], p->kpl[b],
-                                           p->mode[b], stream);
-            if (e != hipSuccess) return e;
+        hipError_t e = hipSuccess;
+        for (const FusedGroup& g : p->groups)
+            if (e == hipSuccess) e = enqueue_fused(p, g, stream);
+        for (size_t b = 0; b < k && e == hipSuccess; ++b) {
+            if (p->fused[b] >= 0) continue;
+            e = lj::enqueue_one(p->descs[b], (char*)p->ws + p->ws_off[b], p->kpl[b],
+                                p->mode[b], stream);
         }
-        return hipSuccess;
+        return e;
     }
     hipError_t e = hipEventRecord(p->fork, stream);
     for (uint32_t r = 0; r < p->branches && e == hipSuccess; ++r)
         e = hipStreamWaitEvent(p->streams[r], p->fork, 0);
-    for (size_t b = 0; b < k && e == hipSuccess; ++b)
+    for (const FusedGroup& g : p->groups)
+        if (e == hipSuccess) e = enqueue_fused(p, g, p->streams[g.branch]);
+    for (size_t b = 0; b < k && e == hipSuccess; ++b) {
+        if (p->fused[b] >= 0) continue;
         e = lj::enqueue_one(p->descs[b], (char*)p->ws + p->ws_off[b], p->kpl[b], p->mode[b],
                             p->streams[p->branch[b]]);
+    }
     for (uint32_t r = 0; r < p->branches && e == hipSuccess; ++r) {
         e = hipEventRecord(p->join[r], p->streams[r]);
         if (e == hipSuccess) e = hipStreamWaitEvent(stream, p->join[r], 0);
@@ -140,22 +170,60 @@ int plan_create(const lj_batch_desc* descs, uint32_t k, const lj_batch_tuning* t
     p->branches = std::min<uint32_t>(t.branches, k);
     p->use_graph = t.use_graph != 0;
 
-    // Workspace slices and keys per lane.
-    uint64_t off = 0;
-    for (uint32_t b = 0; b < k; ++b) {
-        p->ws_off.push_back(off);
-        p->kpl.push_back(t.keys_per_lane[lj::size_class(descs[b].m)]);
-        p->mode.push_back(lj::batch_mode(t, descs[b].m));
-        off = lj::align256(off + lj::ws_bytes(descs[b].index, descs[b].m, p->mode[b]));
-    }
-    // Longest-processing-time assignment of batches to branches.
+    // Workspace slices, keys per lane and probe form; batches that take the
+    // direct probe on a plain RMI join their group's fused launch (when
+    // t.fused), larger batches first in the group's tile-id space.
     std::vector<uint32_t> order(k);
     std::iota(order.begin(), order.end(), 0u);
     std::stable_sort(order.begin(), order.end(),
                      [&](uint32_t a, uint32_t b) { return descs[a].m > descs[b].m; });
+    uint64_t off = 0;
+    p->ws_off.assign(k, 0);
+    p->kpl.assign(k, 0);
+    p->mode.assign(k, 0);
+    p->fused.assign(k, -1);
+    int slot_of_group[4] = {-1, -1, -1, -1};
+    for (uint32_t b : order) {
+        const lj_index* idx = descs[b].index;
+        p->kpl[b] = t.keys_per_lane[lj::size_class(descs[b].m)];
+        p->mode[b] = lj::batch_mode(t, descs[b].m);
+        const int g = lj::fused_group(idx);
+        if (t.fused && descs[b].m > 0 && g >= 0 && !lj::uses_binned(idx, descs[b].m, p->mode[b])) {
+            if (slot_of_group[g] < 0) {
+                slot_of_group[g] = (int)p->groups.size();
+                FusedGroup fg;
+                fg.group = g;
+                p->groups.push_back(fg);
+            }
+            FusedGroup& fg = p->groups[slot_of_group[g]];
+            p->fused[b] = slot_of_group[g];
+            p->kpl[b] = lj::fused_kpl(idx, p->kpl[b]);
+            fg.njobs++;
+            fg.keys += descs[b].m;
+            p->ws_off[b] = off;
+            off = lj::align256(off + lj::fused_job_ws_bytes(descs[b].m, p->kpl[b]));
+        } else {
+            p->ws_off[b] = off;
+            off = lj::align256(off + lj::ws_bytes(idx, descs[b].m, p->mode[b]));
+        }
+    }
+    for (FusedGroup& g : p->groups) {
+        g.hdr_off = off;
+        off = lj::align256(off + lj::kFusedHeader);
+        g.jobs_off = off;
+        off = lj::align256(off + (uint64_t)g.njobs * sizeof(lj::FusedJob));
+    }
+    // Longest-processing-time assignment of the fused launches and the other
+    // batches to branches.
     std::vector<uint64_t> load(p->branches, 0);
     p->branch.assign(k, 0);
+    for (FusedGroup& g : p->groups) {
+        uint32_t r = (uint32_t)(std::min_element(load.begin(), load.end()) - load.begin());
+        g.branch = r;
+        load[r] += g.keys + 1;
+    }
     for (uint32_t b : order) {
+        if (p->fused[b] >= 0) continue;
         uint32_t r = (uint32_t)(std::min_element(load.begin(), load.end()) - load.begin());
         p->branch[b] = r;
         load[r] += descs[b].m + 1;
@@ -166,6 +234,33 @@ int plan_create(const lj_batch_desc* descs, uint32_t k, const lj_batch_tuning* t
         (void)hipGetLastError();
         lj_batch_plan_destroy(p);
         return LJ_ERR_OOM;
+    }
+    // Job tables of the fused launches.
+    for (size_t gi = 0; gi < p->groups.size() && e == hipSuccess; ++gi) {
+        FusedGroup& g = p->groups[gi];
+        std::vector<lj::FusedJob> jobs;
+        uint32_t* hdr = (uint32_t*)((char*)p->ws + g.hdr_off);
+        uint32_t tile0 = 0;
+        for (uint32_t b : order) {
+            if (p->fused[b] != (int)gi) continue;
+            const lj_batch_desc& d = descs[b];
+            jobs.push_back(lj::make_fused_job(d.index, d.s_keys_dev, d.m, d.out_pairs_dev,
+                                              d.out_pairs_dev ? d.out_capacity : 0,
+                                              d.out_count_dev, (char*)p->ws + p->ws_off[b],
+                                              p->kpl[b], hdr + 1, tile0));
+            const uint64_t nt = (uint64_t)tile0 + jobs.back().j.ntiles;
+            if (nt >= (1ull << 31)) e = hipErrorInvalidValue;
+            tile0 = (uint32_t)nt;
+        }
+        g.tiles = tile0;
+        if (e == hipSuccess)
+            e = hipMemcpy((char*)p->ws + g.jobs_off, jobs.data(), jobs.size() * sizeof(jobs[0]),
+                          hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        lj_batch_plan_destroy(p);
+        return LJ_ERR_DEVICE;
     }
     if (p->branches > 1) {
         e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
@@ -277,6 +372,16 @@ int lj_batch_autotune(const lj_batch_desc* descs, uint32_t k, hipStream_t stream
     lj::default_tuning(&best);
     int st = LJ_OK;
     float best_ms = measure(best, &st);
+    // One kernel per batch instead of the fused launches.
+    if (st == LJ_OK) {
+        lj_batch_tuning c = best;
+        c.fused = 0;
+        float ms = measure(c, &st);
+        if (st == LJ_OK && ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
     // Parallel branches, then keys per lane of each size class present.
     for (uint32_t br : {1u, 2u, 8u}) {
         if (st != LJ_OK) break;

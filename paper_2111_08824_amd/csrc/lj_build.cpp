@@ -154,7 +154,7 @@ int fit_rmi(const uint64_t* r, uint64_t n, uint32_t L, uint32_t flags, lj_index*
         rm.frac_bits = 31 - lg;
         const uint64_t full = (uint64_t)L << rm.frac_bits;
         std::vector<uint32_t>& tab = idx->root_tab;
-        tab.assign(kRootBuckets + 1, (uint32_t)full);
+        tab.assign(kRootTabLen, (uint32_t)full);
         for (uint32_t b = 0; b < kRootBuckets && n > 0; ++b) {
             // Lower edge of bucket b as an offset from kmin.
             unsigned __int128 edge;

@@ -149,6 +149,7 @@ constexpr int kItemsDup = 16;
 constexpr int kItemsGapped = 8;
 constexpr int kItemsHash = 8;  // learned hash index: a 64-byte bucket in flight per key
 constexpr int kItemsBinned = 16;  // search kernel of the binned probe (measured best)
+constexpr int kItemsFused = 16;   // largest keys per lane of a fused launch
 constexpr int kSetupChunk = 4;
 constexpr int kMinTile = kBlock * 4;  // smallest tile any launch uses
 
@@ -290,10 +291,41 @@ inline uint32_t job_kind(const lj_index* idx) {
            (idx->gap ? kJobGapped : 0u) | (idx->hash_spk ? kJobHash : 0u);
 }
 
+// One batch of a fused launch (many batches, one kernel): the
+// batch's job, the id of its first tile in the launch's shared tile-id
+// space, and whether its search takes the line-sample stage.  Each batch
+// has a workspace of fused_job_ws_bytes(m, kpl): a done counter, then one
+// look-back status word per tile; the launch shares a kFusedHeader-byte
+// header (tile counter, error flag), which err points into.
+struct FusedJob {
+    TileJob j;
+    uint32_t tile0;
+    uint32_t two_stage;
+    uint64_t pad;
+};
+constexpr uint64_t kFusedJobHeader = 256;
+constexpr uint64_t kFusedHeader = 256;  // word 0: tile counter, word 1: error flag
+inline uint64_t fused_job_ws_bytes(uint64_t m, uint32_t kpl) {
+    return kFusedJobHeader + num_tiles(m, (uint64_t)kBlock * kpl) * 8;
+}
+
 // Kernel launchers (lj_kernels.hip).  Return hipSuccess or the launch error.
 // kpl: keys per lane of the launch (4, 8, 16 or, without duplicates, 24;
 // 0 = the default for the index).
 bool probe_kpl_supported(uint32_t kpl, bool dup);
+// Fused launches: the kernel group of an index (leaf arithmetic and
+// duplicates; -1 for index kinds a fused launch does not take: gapped, hash,
+// exponential search), the keys per lane a batch gets in it, one batch's
+// entry, and the launch itself (clears the header and every batch's
+// workspace first; jobs_dev in device memory, sorted by tile0, all of group
+// `group`).
+int fused_group(const lj_index* idx);
+uint32_t fused_kpl(const lj_index* idx, uint32_t kpl);
+FusedJob make_fused_job(const lj_index* idx, const uint64_t* s, uint64_t m, lj_pair* out,
+                        uint64_t cap, uint64_t* count_out, void* job_ws, uint32_t kpl,
+                        uint32_t* err, uint32_t tile0);
+hipError_t launch_probe_fused(const FusedJob* jobs_dev, uint32_t njobs, uint32_t total_tiles,
+                              int group, uint32_t* hdr, hipStream_t stream);
 hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m,
                         lj_pair* out, uint64_t cap, uint64_t* count_dev,
                         void* ws, hipStream_t stream, hipEvent_t ev0,

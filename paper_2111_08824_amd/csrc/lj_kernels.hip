@@ -77,6 +77,21 @@ __device__ inline LeafF64 load_leaf(const LeafF64* p) {
     return leaf_from(q[0], q[1], q[2]);
 }
 
+// Radix root table in LDS: every thread block that routes keys copies the
+// table (15 KB, kRootTabLen words, a multiple of 4) once, so the two table
+// reads of each routing are LDS reads.  Linear roots need no table.
+__device__ __forceinline__ void stage_root(const RootModel& rm, uint32_t* lds) {
+    if (rm.kind != kRootRadix) return;
+    const uint4* src = (const uint4*)rm.tab_dev;
+    uint4* dst = (uint4*)lds;
+    for (uint32_t i = threadIdx.x; i < kRootTabLen / 4; i += blockDim.x) dst[i] = src[i];
+}
+
+__device__ __forceinline__ uint32_t route_lds(const RootModel& rm, const uint32_t* lds,
+                                              uint64_t x) {
+    return rm.kind == kRootRadix ? route_radix(rm, lds, x) : route(rm, x);
+}
+
 // Shared memory of one tile; the duplicate path needs the per-key offsets
 // and first positions, the unique path only the per-wave counts.
 template <int kItems, bool kWithOffsets>
@@ -98,6 +113,8 @@ __device__ void finish_tile(const TileJob& j) {
             uint32_t e = __hip_atomic_load(j.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             uint64_t tot = ld_status(&j.status[j.ntiles - 1]) & kValMask;
             *j.count_out = e ? ~0ull : tot;
+            // The count may live in pinned host memory (serving loop).
+            __threadfence_system();
         }
     }
 }
@@ -144,10 +161,12 @@ __device__ __forceinline__ void bisect_lockstep(const uint64_t* __restrict__ A,
 template <class Leaf, bool kUnique, int kItems, bool kExp, bool kTwoStage = true>
 __device__ __forceinline__ void search_keys(const uint64_t* __restrict__ R,
                                             const uint64_t* __restrict__ RS, const Leaf* leaves,
-                                            const RootModel& root, const uint64_t* s,
+                                            const RootModel& root, const uint32_t* rtab,
+                                            const uint64_t* s,
                                             const uint64_t m, const uint64_t tbase,
                                             const uint32_t kpl, uint32_t (&first)[kItems],
-                                            uint32_t (&c)[kItems]) {
+                                            uint32_t (&c)[kItems],
+                                            const bool two_stage = kTwoStage) {
     const int tid = threadIdx.x;
     uint64_t x[kItems];
     uint32_t len[kItems];  // binary search: window length
@@ -173,7 +192,8 @@ __device__ __forceinline__ void search_keys(const uint64_t* __restrict__ R,
     for (int k0 = 0; k0 < kItems; k0 += kSetupChunk) {
         Leaf lf[kSetupChunk];
 #pragma unroll
-        for (int u = 0; u < kSetupChunk; ++u) lf[u] = load_leaf(leaves + route(root, x[k0 + u]));
+        for (int u = 0; u < kSetupChunk; ++u)
+            lf[u] = load_leaf(leaves + route_lds(root, rtab, x[k0 + u]));
 #pragma unroll
         for (int u = 0; u < kSetupChunk; ++u) {
             const int k = k0 + u;
@@ -266,7 +286,7 @@ __device__ __forceinline__ void search_keys(const uint64_t* __restrict__ R,
         // key.
         // (The direct probe on an index with short windows searches R in
         // one stage, which takes fewer steps there.)
-        if constexpr (kTwoStage) {
+        if (kTwoStage && two_stage) {
             uint32_t a[kItems], e[kItems];
 #pragma unroll
             for (int k = 0; k < kItems; ++k) {
@@ -355,6 +375,7 @@ __device__ inline uint64_t slot_key(const uint4& v) {
 template <class Leaf, int kItems>
 __device__ __forceinline__ void gapped_setup(const uint32_t nslots, const uint32_t G,
                                              const Leaf* leaves, const RootModel& root,
+                                             const uint32_t* rtab,
                                              const uint64_t* s, const uint64_t m,
                                              const uint64_t tbase, const uint32_t kpl,
                                              uint64_t (&x)[kItems], uint32_t (&a)[kItems],
@@ -372,7 +393,8 @@ __device__ __forceinline__ void gapped_setup(const uint32_t nslots, const uint32
     for (int k0 = 0; k0 < kItems; k0 += kSetupChunk) {
         Leaf lf[kSetupChunk];
 #pragma unroll
-        for (int u = 0; u < kSetupChunk; ++u) lf[u] = load_leaf(leaves + route(root, x[k0 + u]));
+        for (int u = 0; u < kSetupChunk; ++u)
+            lf[u] = load_leaf(leaves + route_lds(root, rtab, x[k0 + u]));
 #pragma unroll
         for (int u = 0; u < kSetupChunk; ++u) {
             const int k = k0 + u;
@@ -442,6 +464,7 @@ template <class Leaf, bool kUnique, int kItems>
 __device__ __forceinline__ void search_keys_gapped(const GSlot* __restrict__ slots,
                                                    const uint32_t nslots, const uint32_t G,
                                                    const Leaf* leaves, const RootModel& root,
+                                                   const uint32_t* rtab,
                                                    const uint64_t* s, const uint64_t m,
                                                    const uint64_t tbase, const uint32_t kpl,
                                                    uint32_t (&first)[kItems],
@@ -449,7 +472,7 @@ __device__ __forceinline__ void search_keys_gapped(const GSlot* __restrict__ slo
     uint64_t x[kItems];
     uint32_t a[kItems], b[kItems], step[kItems];
     uint32_t eqmask = 0;
-    gapped_setup<Leaf, kItems>(nslots, G, leaves, root, s, m, tbase, kpl, x, a, b, step);
+    gapped_setup<Leaf, kItems>(nslots, G, leaves, root, rtab, s, m, tbase, kpl, x, a, b, step);
 #pragma unroll
     for (int k = 0; k < kItems; ++k) first[k] = 0;
     gapped_steps<kItems>(slots, x, a, b, step, eqmask, first);
@@ -505,7 +528,8 @@ __device__ __forceinline__ void search_keys_gapped(const GSlot* __restrict__ slo
 template <class Leaf, bool kUnique, int kItems>
 __device__ __forceinline__ void search_keys_hash(const HBucket* __restrict__ buckets,
                                                  const uint32_t spk, const Leaf* leaves,
-                                                 const RootModel& root, const uint64_t* s,
+                                                 const RootModel& root, const uint32_t* rtab,
+                                                 const uint64_t* s,
                                                  const uint64_t m, const uint64_t tbase,
                                                  const uint32_t kpl, uint32_t (&first)[kItems],
                                                  uint32_t (&c)[kItems]) {
@@ -524,7 +548,8 @@ __device__ __forceinline__ void search_keys_hash(const HBucket* __restrict__ buc
     for (int k0 = 0; k0 < kItems; k0 += kSetupChunk) {
         Leaf lf[kSetupChunk];
 #pragma unroll
-        for (int u = 0; u < kSetupChunk; ++u) lf[u] = load_leaf(leaves + route(root, x[k0 + u]));
+        for (int u = 0; u < kSetupChunk; ++u)
+            lf[u] = load_leaf(leaves + route_lds(root, rtab, x[k0 + u]));
 #pragma unroll
         for (int u = 0; u < kSetupChunk; ++u) {
             const int k = k0 + u;
@@ -697,22 +722,22 @@ constexpr int kSearchOneStage = 4;  // binary search of R without the line-sampl
 
 // Probe one tile of a batch (steps 1-7).
 template <class Leaf, bool kUnique, int kItems, bool kWithOffsets, int kSearch>
-__device__ __forceinline__ void probe_tile(const TileJob& j, const uint32_t tile,
-                                           const uint32_t kpl,
+__device__ __forceinline__ void probe_tile(const TileJob& j, const uint32_t* rtab,
+                                           const uint32_t tile, const uint32_t kpl,
                                            TileShared<kItems, kWithOffsets>& sh) {
     uint32_t first[kItems], c[kItems];
     if constexpr (kSearch == kSearchHash)
         search_keys_hash<Leaf, kUnique, kItems>(j.buckets, j.hash_spk, (const Leaf*)j.leaves,
-                                                j.root, j.s, j.m, (uint64_t)tile * kBlock * kpl,
-                                                kpl, first, c);
+                                                j.root, rtab, j.s, j.m,
+                                                (uint64_t)tile * kBlock * kpl, kpl, first, c);
     else if constexpr (kSearch == kSearchGapped)
         search_keys_gapped<Leaf, kUnique, kItems>(j.slots, j.nslots, j.gap,
-                                                  (const Leaf*)j.leaves, j.root, j.s, j.m,
+                                                  (const Leaf*)j.leaves, j.root, rtab, j.s, j.m,
                                                   (uint64_t)tile * kBlock * kpl, kpl, first, c);
     else
         search_keys<Leaf, kUnique, kItems, kSearch == kSearchExp, kSearch != kSearchOneStage>(
-            j.r, j.rs, (const Leaf*)j.leaves, j.root, j.s, j.m, (uint64_t)tile * kBlock * kpl,
-            kpl, first, c);
+            j.r, j.rs, (const Leaf*)j.leaves, j.root, rtab, j.s, j.m,
+            (uint64_t)tile * kBlock * kpl, kpl, first, c);
     emit_tile<kUnique, kItems, kWithOffsets>(j, tile, kpl, sh, first, c);
 }
 
@@ -720,9 +745,11 @@ template <class Leaf, bool kUnique, int kItems, int kSearch>
 __global__ __launch_bounds__(kBlock) void probe_join_kernel(TileJob j, uint32_t* tile_counter) {
     __shared__ uint32_t s_tile;
     __shared__ TileShared<kItems, !kUnique> sh;
+    __shared__ __align__(16) uint32_t s_root[kRootTabLen];
     if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
+    stage_root(j.root, s_root);
     __syncthreads();
-    probe_tile<Leaf, kUnique, kItems, !kUnique, kSearch>(j, s_tile, kItems, sh);
+    probe_tile<Leaf, kUnique, kItems, !kUnique, kSearch>(j, s_root, s_tile, kItems, sh);
 }
 
 // Search kernel of the binned probe: keys in bin order, tiles of kBlock *
@@ -741,17 +768,21 @@ __global__ __launch_bounds__(kBlock) void probe_binned_kernel(
     const uint32_t slot = blockIdx.x / kXcds;
     const uint32_t tile = (blockIdx.x % kXcds) * tiles_per_xcd + slot;
     if (slot >= tiles_per_xcd || tile >= ntiles) return;
+    __shared__ __align__(16) uint32_t s_root[kRootTabLen];
+    stage_root(root, s_root);
+    __syncthreads();
     const uint64_t tbase = (uint64_t)tile * kBlock * kItems;
     uint32_t first[kItems], c[kItems];
     if constexpr (kSearch == kSearchHash)
-        search_keys_hash<Leaf, kUnique, kItems>(buckets, hash_spk, leaves, root, keys, m, tbase,
-                                                kItems, first, c);
+        search_keys_hash<Leaf, kUnique, kItems>(buckets, hash_spk, leaves, root, s_root, keys, m,
+                                                tbase, kItems, first, c);
     else if constexpr (kSearch == kSearchGapped)
-        search_keys_gapped<Leaf, kUnique, kItems>(slots, nslots, G, leaves, root, keys, m, tbase,
-                                                  kItems, first, c);
+        search_keys_gapped<Leaf, kUnique, kItems>(slots, nslots, G, leaves, root, s_root, keys, m,
+                                                  tbase, kItems, first, c);
     else
-        search_keys<Leaf, kUnique, kItems, kSearch == kSearchExp>(R, RS, leaves, root, keys, m,
-                                                                  tbase, kItems, first, c);
+        search_keys<Leaf, kUnique, kItems, kSearch == kSearchExp>(R, RS, leaves, root, s_root,
+                                                                  keys, m, tbase, kItems, first,
+                                                                  c);
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const uint64_t q = tbase + (uint64_t)k * kBlock + threadIdx.x;
@@ -779,12 +810,16 @@ __global__ __launch_bounds__(kBlock) void probe_binned_gapped_kernel(
     const uint32_t wslot = blockIdx.x / kXcds;
     const uint32_t tile = (blockIdx.x % kXcds) * tiles_per_xcd + wslot;
     if (wslot >= tiles_per_xcd || tile >= ntiles) return;
+    __shared__ __align__(16) uint32_t s_root[kRootTabLen];
+    stage_root(root, s_root);
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const uint64_t tbase = (uint64_t)tile * kBlock * kItems;
     uint64_t x[kItems];
     uint32_t a[kItems], b[kItems], step[kItems], first[kItems];
     uint32_t eqmask = 0;
-    gapped_setup<Leaf, kItems>(nslots, G, leaves, root, keys, m, tbase, kItems, x, a, b, step);
+    gapped_setup<Leaf, kItems>(nslots, G, leaves, root, s_root, keys, m, tbase, kItems, x, a, b,
+                               step);
 #pragma unroll
     for (int k = 0; k < kItems; ++k) first[k] = 0;
     gapped_steps<kItems, kFirstSteps>(slots, x, a, b, step, eqmask, first);
@@ -1057,6 +1092,82 @@ __global__ void predict_windows_kernel(const uint64_t* keys, uint64_t m, const L
         if (wlo) wlo[i] = lo;
         if (whi) whi[i] = hi;
     }
+}
+
+// Fused launch of many batches (one kernel for all the batches of a plan or
+// of a serving batch).  Tiles of all batches share one id space: batch b
+// owns ids [tile0_b, tile0_b + ntiles_b), its tiles in key order, and each
+// thread block takes the next id from the launch's counter, so the
+// look-back of a batch's tile only waits on tiles already handed to running
+// blocks (which publish their aggregates before they wait on anything).
+// The grid holds one block per tile: as blocks retire the dispatcher starts
+// new ones, which keeps every CU's slots filled the way a loop over tile
+// ids in long-lived blocks would; such a loop was tried and costs
+// registers (the compiler keeps loop-invariant constants of the tile shapes
+// live across iterations: 248-256 VGPRs, one wave per SIMD on unique R,
+// against 183 and two waves here).  A tile runs steps 1-7 of probe_tile with its batch's
+// own keys per lane (4, 8 or 16) and line-sample stage, using the LDS of
+// the largest tile shape.
+template <class Leaf, bool kUnique, int kItems, int kMaxItems>
+__device__ __forceinline__ void fused_tile(const TileJob& j, const uint32_t* rtab,
+                                           const uint32_t tile, const bool two_stage,
+                                           char* lds) {
+    using Sh = TileShared<kItems, !kUnique>;
+    static_assert(sizeof(Sh) <= sizeof(TileShared<kMaxItems, !kUnique>), "LDS of a tile");
+    Sh& sh = *reinterpret_cast<Sh*>(lds);
+    uint32_t first[kItems], c[kItems];
+    search_keys<Leaf, kUnique, kItems, false>(j.r, j.rs, (const Leaf*)j.leaves, j.root, rtab,
+                                              j.s, j.m, (uint64_t)tile * kBlock * kItems, kItems,
+                                              first, c, two_stage);
+    emit_tile<kUnique, kItems, !kUnique>(j, tile, kItems, sh, first, c);
+}
+
+template <class Leaf, bool kUnique>
+__global__ __launch_bounds__(kBlock) void probe_fused_kernel(const FusedJob* __restrict__ jobs,
+                                                             uint32_t njobs,
+                                                             uint32_t total_tiles,
+                                                             uint32_t* tile_counter) {
+    constexpr int kMax = kItemsFused;
+    __shared__ __align__(16) char lds[sizeof(TileShared<kMax, !kUnique>)];
+    __shared__ __align__(16) uint32_t s_root[kRootTabLen];
+    __shared__ uint32_t s_tile, s_job;
+    if (threadIdx.x == 0) {
+        const uint32_t t = atomicAdd(tile_counter, 1u);  // < total_tiles: one block per tile
+        uint32_t lo = 0, hi = njobs;  // the last batch whose first tile id is <= t
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (jobs[mid].tile0 <= t) lo = mid;
+            else hi = mid;
+        }
+        s_tile = t;
+        s_job = lo;
+    }
+    __syncthreads();
+    const uint32_t t = __builtin_amdgcn_readfirstlane(s_tile);
+    const uint32_t b = __builtin_amdgcn_readfirstlane(s_job);
+    if (t >= total_tiles) return;  // cannot happen: the grid has total_tiles blocks
+    const TileJob& j = jobs[b].j;
+    stage_root(j.root, s_root);
+    __syncthreads();
+    const uint32_t tile = t - jobs[b].tile0;
+    const bool two = jobs[b].two_stage != 0;
+    switch (j.kpl) {
+        case 4: fused_tile<Leaf, kUnique, 4, kMax>(j, s_root, tile, two, lds); break;
+        case 8: fused_tile<Leaf, kUnique, 8, kMax>(j, s_root, tile, two, lds); break;
+        default: fused_tile<Leaf, kUnique, 16, kMax>(j, s_root, tile, two, lds); break;
+    }
+}
+
+// Clears what a fused launch needs zeroed: the shared header (tile counter,
+// error flag) and every batch's done counter and look-back status words.
+// One block per batch; block 0 also clears the header.
+__global__ void zero_fused_kernel(const FusedJob* __restrict__ jobs, uint32_t* hdr_words,
+                                  uint32_t hdr_count) {
+    const FusedJob& fj = jobs[blockIdx.x];
+    if (blockIdx.x == 0)
+        for (uint32_t i = threadIdx.x; i < hdr_count; i += blockDim.x) hdr_words[i] = 0u;
+    if (threadIdx.x == 0) *fj.j.done = 0u;
+    for (uint32_t i = threadIdx.x; i < fj.j.ntiles; i += blockDim.x) fj.j.status[i] = 0ull;
 }
 
 unsigned grid_for(uint64_t work, unsigned block) {
@@ -1338,6 +1449,70 @@ hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m, lj_p
     if (e != hipSuccess) return e;
     if (ev1) e = hipEventRecord(ev1, stream);
     return e;
+}
+
+int fused_group(const lj_index* idx) {
+    const uint32_t kind = job_kind(idx);
+    if (kind & (kJobExp | kJobGapped | kJobHash)) return -1;
+    return (int)(kind & (kJobFp64 | kJobDup));
+}
+
+uint32_t fused_kpl(const lj_index* idx, uint32_t kpl) {
+    (void)idx;
+    if (kpl != 4 && kpl != 8 && kpl != 16 && kpl != 24) kpl = 16;
+    return kpl < (uint32_t)kItemsFused ? kpl : (uint32_t)kItemsFused;
+}
+
+FusedJob make_fused_job(const lj_index* idx, const uint64_t* s, uint64_t m, lj_pair* out,
+                        uint64_t cap, uint64_t* count_out, void* job_ws, uint32_t kpl,
+                        uint32_t* err, uint32_t tile0) {
+    FusedJob f{};
+    f.j = index_job(idx);
+    f.j.s = s;
+    f.j.m = m;
+    f.j.out = out;
+    f.j.cap = out ? cap : 0;
+    f.j.count_out = count_out;
+    f.j.done = (uint32_t*)job_ws;
+    f.j.status = (uint64_t*)((char*)job_ws + kFusedJobHeader);
+    f.j.err = err;
+    f.j.kpl = fused_kpl(idx, kpl);
+    f.j.ntiles = (uint32_t)num_tiles(m, (uint64_t)kBlock * f.j.kpl);
+    f.tile0 = tile0;
+    f.two_stage = direct_search_mode(idx, f.j.kind) == kSearchBinary ? 1u : 0u;
+    return f;
+}
+
+namespace {
+
+template <class Leaf, bool kUnique>
+hipError_t launch_fused_typed(const FusedJob* jobs, uint32_t njobs, uint32_t total_tiles,
+                              uint32_t* tile_counter, hipStream_t stream) {
+    hipLaunchKernelGGL((probe_fused_kernel<Leaf, kUnique>), dim3(total_tiles), dim3(kBlock), 0,
+                       stream, jobs, njobs, total_tiles, tile_counter);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_probe_fused(const FusedJob* jobs_dev, uint32_t njobs, uint32_t total_tiles,
+                              int group, uint32_t* hdr, hipStream_t stream) {
+    if (njobs == 0 || total_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_fused_kernel, dim3(njobs), dim3(256), 0, stream, jobs_dev, hdr,
+                       (uint32_t)(kFusedHeader / 4));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    uint32_t* ctr = hdr;
+    switch (group) {
+        case 0: return launch_fused_typed<LeafF32, true>(jobs_dev, njobs, total_tiles, ctr, stream);
+        case kJobDup:
+            return launch_fused_typed<LeafF32, false>(jobs_dev, njobs, total_tiles, ctr, stream);
+        case kJobFp64:
+            return launch_fused_typed<LeafF64, true>(jobs_dev, njobs, total_tiles, ctr, stream);
+        case kJobFp64 | kJobDup:
+            return launch_fused_typed<LeafF64, false>(jobs_dev, njobs, total_tiles, ctr, stream);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_self_check(const lj_index* idx, uint64_t* viol, hipStream_t stream) {

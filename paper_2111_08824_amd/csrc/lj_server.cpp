@@ -86,7 +86,13 @@ struct Slot {
     hipStream_t stream = nullptr;      // copies in, probes, counts out
     hipStream_t ret_stream = nullptr;  // pairs back to the host
     std::vector<hipEvent_t> events;    // one per request of a batch
+    std::vector<uint32_t> ev_of;       // event that completes each request of the batch
     uint64_t* counts_host = nullptr;   // pinned, one per request of a batch
+    uint64_t* counts_dev = nullptr;    // the same memory as the device addresses it
+    // Fused launch of the batch's direct probes: job tables staged in pinned
+    // memory and copied to fused_dev (launch headers, then the tables).
+    lj::FusedJob* jobs_host = nullptr;
+    char* fused_dev = nullptr;
     std::vector<Request*> batch;
     bool busy = false;
     bool has_work = false;
@@ -116,6 +122,7 @@ struct lj_server {
     void schedule_loop();
     void slot_loop(Slot* s);
     hipError_t enqueue_batch(Slot* s);
+    uint32_t grp_tiles_[4] = {0, 0, 0, 0};  // scratch of enqueue_batch (scheduler thread)
 };
 
 namespace {
@@ -147,17 +154,80 @@ uint64_t footprint(const lj_index* idx, uint64_t m, uint64_t cap, Request* r) {
 
 }  // namespace
 
-// Per request, in batch order: keys in (host requests), probe, count out,
-// then an event, so that the completion thread can return each request as
-// soon as its own work is done.
+// The batch on its slot's stream: the keys of host requests in; one fused
+// launch per kernel group for every request probed directly on a plain RMI
+// (their counts written by the kernel straight into the slot's pinned count
+// words), followed by one event that completes them all; then every other
+// request (binned probes, gapped and hash indexes, empty requests) with its
+// own probe, count copy and event, so that the completion thread can return
+// each request as soon as its own work is done.
 hipError_t lj_server::enqueue_batch(Slot* s) {
     hipError_t e = hipSuccess;
-    for (size_t i = 0; i < s->batch.size() && e == hipSuccess; ++i) {
+    const size_t nb = s->batch.size();
+    s->ev_of.assign(nb, 0);
+    std::vector<int> grp(nb, -1);
+    for (size_t i = 0; i < nb && e == hipSuccess; ++i) {
         Request* r = s->batch[i];
         char* base = arena_base + r->off;
         if (r->m && !r->on_device)  // device requests bring their keys in place
             e = hipMemcpyAsync(base + r->s_off, r->s_host, 8 * r->m, hipMemcpyHostToDevice,
                                s->stream);
+        const lj_index* idx = indexes[r->index_id];
+        if (cfg.fused && r->m > 0 && !lj::uses_binned(idx, r->m, r->mode))
+            grp[i] = lj::fused_group(idx);
+    }
+    // Fused launches: jobs grouped by kernel group, larger requests first.
+    std::vector<uint32_t> order;
+    for (size_t i = 0; i < nb; ++i)
+        if (grp[i] >= 0) order.push_back((uint32_t)i);
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        return grp[a] != grp[b] ? grp[a] < grp[b] : s->batch[a]->m > s->batch[b]->m;
+    });
+    if (!order.empty() && e == hipSuccess) {
+        lj::FusedJob* jobs_dev = (lj::FusedJob*)(s->fused_dev + 4 * lj::kFusedHeader);
+        size_t a = 0;
+        while (a < order.size()) {
+            size_t z = a;
+            uint32_t tile0 = 0;
+            uint32_t* hdr = (uint32_t*)(s->fused_dev + grp[order[a]] * lj::kFusedHeader);
+            while (z < order.size() && grp[order[z]] == grp[order[a]]) {
+                const uint32_t i = order[z];
+                Request* r = s->batch[i];
+                char* base = arena_base + r->off;
+                const lj_index* idx = indexes[r->index_id];
+                lj_pair* out = !r->devcap ? nullptr
+                               : r->on_device ? r->out_host
+                                              : (lj_pair*)(base + r->out_off);
+                s->jobs_host[z] = lj::make_fused_job(
+                    idx, r->on_device ? r->s_host : (const uint64_t*)(base + r->s_off), r->m,
+                    out, r->devcap, &s->counts_dev[i], base + r->ws_off,
+                    cfg.keys_per_lane[lj::size_class(r->m)], hdr + 1, tile0);
+                tile0 += s->jobs_host[z].j.ntiles;
+                ++z;
+            }
+            grp_tiles_[grp[order[a]]] = tile0;
+            a = z;
+        }
+        e = hipMemcpyAsync(jobs_dev, s->jobs_host, order.size() * sizeof(lj::FusedJob),
+                           hipMemcpyHostToDevice, s->stream);
+        a = 0;
+        while (a < order.size() && e == hipSuccess) {
+            size_t z = a;
+            while (z < order.size() && grp[order[z]] == grp[order[a]]) ++z;
+            const int g = grp[order[a]];
+            e = lj::launch_probe_fused(jobs_dev + a, (uint32_t)(z - a), grp_tiles_[g], g,
+                                       (uint32_t*)(s->fused_dev + g * lj::kFusedHeader),
+                                       s->stream);
+            a = z;
+        }
+        if (e == hipSuccess) e = hipEventRecord(s->events[order[0]], s->stream);
+        for (uint32_t i : order) s->ev_of[i] = order[0];
+    }
+    for (size_t i = 0; i < nb && e == hipSuccess; ++i) {
+        if (grp[i] >= 0) continue;
+        Request* r = s->batch[i];
+        char* base = arena_base + r->off;
+        s->ev_of[i] = (uint32_t)i;
         lj_batch_desc d;
         d.index = indexes[r->index_id];
         d.s_keys_dev = r->on_device ? r->s_host : (const uint64_t*)(base + r->s_off);
@@ -245,7 +315,8 @@ void lj_server::slot_loop(Slot* s) {
         // Return requests one by one, as their own work finishes.
         for (size_t i = 0; i < batch.size(); ++i) {
             Request* r = batch[i];
-            bool ok = r->res.status == LJ_OK && hipEventSynchronize(s->events[i]) == hipSuccess;
+            bool ok = r->res.status == LJ_OK &&
+                      hipEventSynchronize(s->events[s->ev_of[i]]) == hipSuccess;
             uint64_t count = ok ? s->counts_host[i] : ~0ull;
             if (ok && count != ~0ull && !r->on_device) {
                 uint64_t n = std::min(count, std::min(r->cap, r->devcap));
@@ -293,6 +364,7 @@ void lj_server_default_config(lj_server_config* c, uint64_t budget_bytes) {
     c->keys_per_lane[2] = 16;
     c->keys_per_lane[3] = 24;
     c->binned_min_keys = 0;
+    c->fused = 1;
 }
 
 int lj_server_create(lj_index* const* indexes, uint32_t n, const lj_server_config* cfg,
@@ -300,7 +372,8 @@ int lj_server_create(lj_index* const* indexes, uint32_t n, const lj_server_confi
     if (!out) return LJ_ERR_ARG;
     *out = nullptr;
     if (!indexes || n == 0 || !cfg || cfg->budget_bytes == 0 || cfg->slots < 1 ||
-        cfg->slots > 16 || cfg->max_batch_requests < 1 || cfg->max_batch_keys < 1)
+        cfg->slots > 16 || cfg->max_batch_requests < 1 || cfg->max_batch_keys < 1 ||
+        cfg->fused > 1)
         return LJ_ERR_ARG;
     lj_batch_tuning t;
     lj::default_tuning(&t);
@@ -332,7 +405,14 @@ int lj_server_create(lj_index* const* indexes, uint32_t n, const lj_server_confi
         if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
             hipStreamCreateWithFlags(&s->ret_stream, hipStreamNonBlocking) != hipSuccess ||
             hipHostMalloc((void**)&s->counts_host, 8ull * cfg->max_batch_requests) !=
+                hipSuccess ||
+            hipHostGetDevicePointer((void**)&s->counts_dev, s->counts_host, 0) != hipSuccess ||
+            hipHostMalloc((void**)&s->jobs_host,
+                          sizeof(lj::FusedJob) * cfg->max_batch_requests) != hipSuccess ||
+            hipMalloc((void**)&s->fused_dev, 4 * lj::kFusedHeader +
+                                                 sizeof(lj::FusedJob) * cfg->max_batch_requests) !=
                 hipSuccess) {
+            (void)hipGetLastError();
             st = LJ_ERR_DEVICE;
             break;
         }
@@ -453,6 +533,8 @@ void lj_server_destroy(lj_server* sv) {
         if (s->ret_stream) (void)hipStreamDestroy(s->ret_stream);
         for (hipEvent_t ev : s->events) (void)hipEventDestroy(ev);
         if (s->counts_host) (void)hipHostFree(s->counts_host);
+        if (s->jobs_host) (void)hipHostFree(s->jobs_host);
+        if (s->fused_dev) (void)hipFree(s->fused_dev);
         delete s;
     }
     for (auto& kv : sv->requests) delete kv.second;

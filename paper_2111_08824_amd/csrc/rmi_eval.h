@@ -38,6 +38,9 @@ constexpr uint32_t kRootLinear = 0;
 constexpr uint32_t kRootRadix = 1;
 constexpr uint32_t kRootSubBits = 6;
 constexpr uint32_t kRootBuckets = (64 - kRootSubBits + 1) << kRootSubBits;  // 3776
+// Table length: kRootBuckets + 1 edges, padded to a multiple of 4 words
+// (the padding repeats the last edge).
+constexpr uint32_t kRootTabLen = (kRootBuckets + 1 + 3) & ~3u;
 struct RootModel {
     double a0;
     double b0;
@@ -46,7 +49,7 @@ struct RootModel {
     uint32_t kind;       // kRootLinear or kRootRadix
     uint32_t frac_bits;  // radix: fraction bits of the table's coordinates
     uint32_t pad;
-    const uint32_t* tab_host;  // radix: kRootBuckets + 1 coordinates
+    const uint32_t* tab_host;  // radix: kRootTabLen coordinates
     const uint32_t* tab_dev;
 };
 

@@ -93,12 +93,13 @@ class lj_batch_tuning(ctypes.Structure):
         ("use_graph", ctypes.c_uint32),
         ("binned_min_keys", ctypes.c_uint64),
         ("measured_ms", ctypes.c_float),
+        ("fused", ctypes.c_uint32),
     ]
 
     def as_dict(self):
         return {"keys_per_lane": list(self.keys_per_lane), "branches": self.branches,
                 "use_graph": self.use_graph, "binned_min_keys": self.binned_min_keys,
-                "measured_ms": self.measured_ms}
+                "fused": self.fused, "measured_ms": self.measured_ms}
 
 
 class lj_server_config(ctypes.Structure):
@@ -109,6 +110,8 @@ class lj_server_config(ctypes.Structure):
         ("max_batch_keys", ctypes.c_uint64),
         ("keys_per_lane", ctypes.c_uint32 * 4),
         ("binned_min_keys", ctypes.c_uint64),
+        ("fused", ctypes.c_uint32),
+        ("pad", ctypes.c_uint32),
     ]
 
 

@@ -42,18 +42,20 @@ def _check(items):
         assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("fused", [1, 0])
 @pytest.mark.parametrize("use_graph", [0, 1])
 @pytest.mark.parametrize("binned_min_keys", [0, 1, 5000])
-def test_plan_matches_oracle_on_every_replay(use_graph, binned_min_keys):
+def test_plan_matches_oracle_on_every_replay(use_graph, binned_min_keys, fused):
     import torch
     items = _mixed_batches()
     t = lj.lj_batch_default_tuning()
     t.use_graph = use_graph
+    t.fused = fused  # one kernel for the direct batches of each kernel group, or one per batch
     t.binned_min_keys = binned_min_keys  # index flags / every batch binned / large ones
     plan = lj.BatchPlan([(ix, s, out, cnt) for _, _, ix, s, out, cnt in items], t)
     for rep in range(3):
-        print(f"[batches] replay {rep} graph={use_graph} binned_min_keys={binned_min_keys}",
-              flush=True)
+        print(f"[batches] replay {rep} graph={use_graph} binned_min_keys={binned_min_keys} "
+              f"fused={fused}", flush=True)
         for *_, out, cnt in items:  # eager work between replays
             out.fill_(-1)
             cnt.fill_(-7)
@@ -116,6 +118,45 @@ def test_autotune_then_plan():
     plan.run()
     torch.cuda.synchronize()
     _check(items)
+
+
+@pytest.mark.parametrize("kpl", [4, 8, 16, 24])
+def test_fused_plan_tile_shapes_and_many_batches(kpl):
+    # Many small and ragged batches of every kernel group (FP32 / FP64
+    # leaves, unique / duplicate keys, linear and radix roots) in one fused
+    # plan; each size class with the given keys per lane (24 runs as 16).
+    import torch
+    rng = np.random.default_rng(kpl)
+    items = []
+    for i in range(40):
+        n = int(rng.integers(1, 60_000))
+        if i % 5 == 4:
+            R = np.repeat(workloads.gen.uniform_unique(max(1, n // 4), 30, i), 4)
+        else:
+            R = workloads.gen.uniform_unique(n, 30, i)
+        m = int(rng.choice([1, 255, 1023, 1024, 1025, 4097, 20_000, 70_001]))
+        S = workloads.gen.probe_mix(R, m, 0.5, 1000 + i, miss_hi=2**30)
+        flags = (lj.LJ_LEAF_FP64 if i % 3 == 0 else lj.LJ_LEAF_FP32) | \
+            (lj.LJ_ROOT_RADIX if i % 2 else 0)
+        ix = lj.lj_build_rmi(R, max(1, n // 200), flags)
+        cap = max(1, m * int(ix.stats.max_mult))
+        s = lj.to_device_keys(S)
+        out = torch.full((cap, 2), -1, dtype=torch.int32, device="cuda")
+        cnt = torch.full((1,), -7, dtype=torch.int64, device="cuda")
+        items.append((R, S, ix, s, out, cnt))
+    t = lj.lj_batch_default_tuning()
+    t.keys_per_lane[:] = [kpl] * 4
+    t.fused = 1
+    plan = lj.BatchPlan([(ix, s, out, cnt) for _, _, ix, s, out, cnt in items], t)
+    for rep in range(2):
+        print(f"[batches] fused kpl={kpl} replay {rep}", flush=True)
+        for *_, out, cnt in items:
+            out.fill_(-1)
+            cnt.fill_(-7)
+        plan.run()
+        torch.cuda.synchronize()
+        _check(items)
+    plan.close()
 
 
 def test_plan_argument_errors():

@@ -45,12 +45,14 @@ def _alone(ix, S):
     return lj.probe(ix, lj.to_device_keys(S)).cpu().numpy().view(np.uint32)
 
 
+@pytest.mark.parametrize("fused", [1, 0])
 @pytest.mark.parametrize("budget,slots", [(1 << 23, 3), (1 << 30, 4)])
-def test_results_alone_equal_results_in_the_mix(budget, slots):
+def test_results_alone_equal_results_in_the_mix(budget, slots, fused):
     ws, ixs = _indexes()
     reqs = _requests(ws, 80, seed=budget % 97)
     cfg = lj.lj_server_default_config(budget)
     cfg.slots = slots
+    cfg.fused = fused
     srv = lj.Server(ixs, cfg)
     tickets = [None] * len(reqs)
     rng = np.random.default_rng(5)
