@@ -2,12 +2,14 @@
 """Benchmark of the learned indexed nested loop join probe on one MI355X.
 
 One step = one synchronous probe (lj_probe_join) of the whole outer relation
-S against the two-level linear RMI over R: root model, leaf model, bounded
+S against the two-level RMI over R: root model, linear leaf model, bounded
 last-mile search, match counting, output compaction and pair emission, plus
 the 8-byte count readback.  R, the index and S are resident in HBM before
 the timed region; building the index is offline (untimed).  By default the
 probe is the binned one (S partitioned by key range of R first, the same
-pairs in the same order); --probe direct probes S in its own order.
+pairs in the same order); --probe direct probes S in its own order.  The
+root is the radix-table root by default (--root linear: one least-squares
+line).
 
 Default workload: R = 2e8 distinct lognormal(0, 2) keys scaled to 2^63,
 2^20 leaves with FP32 leaf models; S = 2e8 keys, 90% Zipf(1) hits.
@@ -550,10 +552,40 @@ def bench_serving(args) -> None:
         pin_o = torch.empty((nbuf, max_m, 2), dtype=torch.int32, pin_memory=True)
         o_np = pin_o.numpy().view(np.uint32)
 
+    if on_device:
+        o_all = torch.empty((nreq * (max_m // 8) + max_m, 2), dtype=torch.int32, device="cuda")
+
+    def run_native(cfg, reqs, rate):
+        """Device requests submitted by the library's own load driver
+        (lj_server_replay: a native thread submits at the arrival times,
+        another waits), so that the client costs nothing per request."""
+        srv = lj.Server(ixs, cfg)
+        items, off = [], 0
+        for i, a, m in reqs:
+            if off + m > o_all.shape[0]:
+                off = 0  # reuse: pairs of early requests are not read back
+            items.append((i, s_dev[i, a:a + m], o_all[off:off + m]))
+            off += m
+        arrival = None
+        if rate:
+            arrival = np.cumsum(rng.exponential(1.0 / rate, len(reqs))) * 1e9
+        torch.cuda.synchronize()
+        start = time.perf_counter()
+        res = srv.replay(items, arrival)
+        wall = time.perf_counter() - start
+        assert all(r.status == lj.LJ_OK for r in res)
+        lat = np.array([(r.done_ns - r.submit_ns) * 1e-6 for r in res])
+        pairs = sum(int(r.count) for r in res)
+        st = srv.stats
+        srv.close()
+        return wall, lat, st, pairs
+
     def run(cfg, reqs, rate):
         """Submit reqs (Poisson arrivals at `rate` per second, or all at once
         when rate is None); returns (wall seconds, latencies in ms, stats,
         total pairs)."""
+        if on_device and args.driver == "native":
+            return run_native(cfg, reqs, rate)
         srv = lj.Server(ixs, cfg)
         free = pyqueue.Queue()
         for b in range(nbuf):
@@ -667,7 +699,8 @@ def bench_serving(args) -> None:
         "config": {"workload": "serving-8x50M", "indexes": 8, "inner_keys_each": 50_000_000,
                    "leaf_model": "fp32", "root": args.root,
                    "request_keys": "log-uniform 256..4194304", "requests_per_load": nreq,
-                   "request_buffers": args.request_buffers, "server": best},
+                   "request_buffers": args.request_buffers, "server": best,
+                   "driver": args.driver if on_device else "python"},
         "saturation": {**{f"{n}_probes_per_s": keys_sat / sat[n][0] for n, _ in configs},
                        "served_max_batch": int(st_sat.max_batch_size),
                        "served_speedup_vs_plain": round(w_plain / w_served, 3)},
@@ -911,7 +944,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lognormal-zipf-200M")
     ap.add_argument("--leaf", choices=["fp32", "fp64"], default="fp32")
-    ap.add_argument("--root", choices=["linear", "radix"], default="linear",
+    ap.add_argument("--root", choices=["linear", "radix"], default="radix",
                     help="root model: one least-squares line, or a piecewise-linear CDF "
                          "over a radix table of the key")
     ap.add_argument("--search", choices=["binary", "exponential"], default="binary",
@@ -939,6 +972,9 @@ def main():
     ap.add_argument("--request-buffers", choices=["host", "device"], default="device",
                     help="serving workload: request keys and pairs already in device "
                          "memory, or in pinned host memory (copied over PCIe)")
+    ap.add_argument("--driver", choices=["native", "python"], default="native",
+                    help="serving workload with device buffers: requests submitted by the "
+                         "library's native load driver, or one by one from Python threads")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the steps, run a plain device copy of this many MiB "
                          "(reference point for HBM byte counters)")

@@ -437,6 +437,30 @@ int lj_server_submit_device(lj_server* server, uint32_t index_id,
 int lj_server_wait(lj_server* server, uint64_t ticket, int64_t timeout_ms,
                    lj_request_result* result);
 
+/*
+ * Load driver for device-resident requests (measurement of the serving loop
+ * without a client's own per-request cost): the calling thread submits the
+ * n requests with lj_server_submit_device, each at its arrival time
+ * (arrival_ns after the call starts, non-decreasing; 0 for all at once),
+ * while a second thread waits for them in submission order; returns when
+ * every request has completed, with request i's result in results[i] (its
+ * own status inside).  Errors: LJ_ERR_ARG (null pointers, decreasing
+ * arrival times, or a submission refused: results of the requests before it
+ * are valid), LJ_ERR_OOM.
+ */
+typedef struct {
+    uint32_t index_id;
+    uint32_t pad;
+    const uint64_t* s_keys_dev;
+    uint64_t m;
+    lj_pair* out_pairs_dev;   /* NULL with out_capacity 0 for count only */
+    uint64_t out_capacity;
+    uint64_t arrival_ns;
+} lj_replay_request;
+
+int lj_server_replay(lj_server* server, const lj_replay_request* requests, uint64_t n,
+                     lj_request_result* results);
+
 int lj_server_get_stats(lj_server* server, lj_server_stats* out);
 
 /* Finish every submitted request, stop the threads and free the arena. */

@@ -507,6 +507,55 @@ int lj_server_wait(lj_server* sv, uint64_t ticket, int64_t timeout_ms, lj_reques
     return LJ_OK;
 }
 
+int lj_server_replay(lj_server* sv, const lj_replay_request* reqs, uint64_t n,
+                     lj_request_result* results) {
+    if (!sv || (n && (!reqs || !results))) return LJ_ERR_ARG;
+    for (uint64_t i = 1; i < n; ++i)
+        if (reqs[i].arrival_ns < reqs[i - 1].arrival_ns) return LJ_ERR_ARG;
+    std::vector<uint64_t> tickets;
+    try {
+        tickets.assign(n, 0);
+    } catch (const std::bad_alloc&) {
+        return LJ_ERR_OOM;
+    }
+    std::mutex mu;
+    std::condition_variable cv;
+    uint64_t submitted = 0;  // requests with a ticket (guarded by mu)
+    bool failed = false;
+    std::thread collector([&] {
+        for (uint64_t i = 0; i < n; ++i) {
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv.wait(lk, [&] { return submitted > i || failed; });
+                if (submitted <= i) return;
+            }
+            (void)lj_server_wait(sv, tickets[i], -1, &results[i]);
+        }
+    });
+    const uint64_t start = now_ns();
+    int st = LJ_OK;
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t due = start + reqs[i].arrival_ns;
+        for (uint64_t t = now_ns(); t < due; t = now_ns()) {
+            if (due - t > 200000) std::this_thread::sleep_for(std::chrono::nanoseconds(due - t - 100000));
+        }
+        uint64_t ticket = 0;
+        st = submit(sv, reqs[i].index_id, reqs[i].s_keys_dev, reqs[i].m, reqs[i].out_pairs_dev,
+                    reqs[i].out_pairs_dev ? reqs[i].out_capacity : 0, true, &ticket);
+        std::lock_guard<std::mutex> lk(mu);
+        if (st != LJ_OK) {
+            failed = true;
+            cv.notify_all();
+            break;
+        }
+        tickets[i] = ticket;
+        submitted = i + 1;
+        cv.notify_all();
+    }
+    collector.join();
+    return st == LJ_OK ? LJ_OK : LJ_ERR_ARG;
+}
+
 int lj_server_get_stats(lj_server* sv, lj_server_stats* out) {
     if (!sv || !out) return LJ_ERR_ARG;
     std::lock_guard<std::mutex> lk(sv->mu);

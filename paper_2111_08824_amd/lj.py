@@ -40,7 +40,8 @@ EXPORTED = (
     "lj_bench_random_gather", "lj_strerror", "lj_batch_default_tuning",
     "lj_batch_plan_create", "lj_batch_plan_run", "lj_batch_plan_destroy", "lj_batch_autotune",
     "lj_server_default_config", "lj_server_create", "lj_server_submit",
-    "lj_server_submit_device", "lj_server_wait", "lj_server_get_stats", "lj_server_destroy",
+    "lj_server_submit_device", "lj_server_wait", "lj_server_replay", "lj_server_get_stats",
+    "lj_server_destroy",
     "lj_build_gapped_rmi", "lj_build_gapped_rmi_host_only", "lj_gapped_slots_host",
     "lj_build_learned_hash", "lj_build_learned_hash_host_only", "lj_hash_buckets_host",
     "lj_sort_join_workspace_bytes", "lj_sort_join_async", "lj_learned_sort_async",
@@ -126,6 +127,18 @@ class lj_request_result(ctypes.Structure):
     ]
 
 
+class lj_replay_request(ctypes.Structure):
+    _fields_ = [
+        ("index_id", ctypes.c_uint32),
+        ("pad", ctypes.c_uint32),
+        ("s_keys_dev", ctypes.c_void_p),
+        ("m", ctypes.c_uint64),
+        ("out_pairs_dev", ctypes.c_void_p),
+        ("out_capacity", ctypes.c_uint64),
+        ("arrival_ns", ctypes.c_uint64),
+    ]
+
+
 class lj_server_stats(ctypes.Structure):
     _fields_ = [
         ("requests_done", ctypes.c_uint64),
@@ -188,6 +201,8 @@ def lib() -> ctypes.CDLL:
         L.lj_server_submit.argtypes = [vp, u32, vp, u64, vp, u64, ctypes.POINTER(u64)]
         L.lj_server_submit_device.argtypes = [vp, u32, vp, u64, vp, u64, ctypes.POINTER(u64)]
         L.lj_server_wait.argtypes = [vp, u64, ctypes.c_int64, ctypes.POINTER(lj_request_result)]
+        L.lj_server_replay.argtypes = [vp, ctypes.POINTER(lj_replay_request), u64,
+                                       ctypes.POINTER(lj_request_result)]
         L.lj_server_get_stats.argtypes = [vp, ctypes.POINTER(lj_server_stats)]
         L.lj_server_destroy.argtypes = [vp]
         L.lj_server_destroy.restype = None
@@ -206,7 +221,7 @@ def lib() -> ctypes.CDLL:
                   "lj_probe_set_timing_events", "lj_bench_random_gather",
                   "lj_batch_plan_create", "lj_batch_plan_run", "lj_batch_autotune",
                   "lj_server_create", "lj_server_submit", "lj_server_submit_device",
-                  "lj_server_wait",
+                  "lj_server_wait", "lj_server_replay",
                   "lj_server_get_stats", "lj_sort_join_async", "lj_learned_sort_async",
                   "lj_probe_join_noalloc"):
             getattr(L, f).restype = i32
@@ -590,6 +605,25 @@ class Server:
         _check(lib().lj_server_wait(self.handle, ticket, timeout_ms, ctypes.byref(r)),
                "lj_server_wait")
         return r
+
+    def replay(self, requests, arrival_ns=None):
+        """Submit device-resident requests from a native thread at their
+        arrival times (ns after the start; None = all at once) and wait for
+        them all.  requests: list of (index_id, s_keys_dev, out_pairs_dev or
+        None).  Returns the list of lj_request_result."""
+        n = len(requests)
+        arr = (lj_replay_request * n)()
+        for i, (ix, s, out) in enumerate(requests):
+            r = arr[i]
+            r.index_id = ix
+            r.m = s.numel()
+            r.s_keys_dev = _dev_ptr(s) if r.m else None
+            r.out_capacity = 0 if out is None else out.shape[0]
+            r.out_pairs_dev = _dev_ptr(out) if r.out_capacity else None
+            r.arrival_ns = 0 if arrival_ns is None else int(arrival_ns[i])
+        res = (lj_request_result * n)()
+        _check(lib().lj_server_replay(self.handle, arr, n, res), "lj_server_replay")
+        return list(res)
 
     @property
     def stats(self) -> lj_server_stats:

@@ -231,3 +231,26 @@ def test_windows_around_line_boundaries(n):
             assert_parity(R, S, leaves, flags, f"line boundaries n={n}")
     D = np.repeat(R, 3)  # runs of three equal keys across line ends
     assert_parity(D, S, 1, lj.LJ_LEAF_FP32, f"line boundaries dup n={n}")
+
+
+@pytest.mark.parametrize("binned", [0, BIN])
+def test_radix_root_clusters_big_leaves_and_runs(binned):
+    # Radix root on: (1) clusters of keys a few apart spread over [0, 2^60)
+    # (many keys share a root bucket's interpolation); (2) one key repeated
+    # 600 times beside ordinary keys (one leaf far larger than the rest);
+    # (3) runs of equal keys across line ends.
+    rng = np.random.default_rng(77)
+    base = np.sort(rng.choice(2**60, 3000, replace=False).astype(np.uint64))
+    R1 = np.unique(np.concatenate([base + np.uint64(j) for j in range(0, 40, 3)]))
+    S1 = np.concatenate([R1[::5], R1[::7] + np.uint64(1), base - np.uint64(1),
+                         rng.integers(0, 2**60, 20_000, dtype=np.uint64)])
+    R2 = np.sort(np.concatenate([workloads.gen.uniform_unique(100_000, 40, 5),
+                                 np.full(600, 2**39 + 12345, dtype=np.uint64)]))
+    S2 = np.concatenate([R2[::3], np.full(50, 2**39 + 12345, dtype=np.uint64),
+                         rng.integers(0, 2**40, 30_000, dtype=np.uint64)])
+    R3 = np.repeat(np.arange(0, 30_000, 2, dtype=np.uint64), 5)  # runs of 5 across lines
+    S3 = np.arange(0, 30_010, dtype=np.uint64)
+    for R, S, label in ((R1, S1, "ties"), (R2, S2, "big leaf"), (R3, S3, "runs")):
+        for leaves in (max(1, len(R) // 200), max(1, len(R) // 50)):
+            assert_parity(R, S, leaves, lj.LJ_LEAF_FP32 | RADIX | binned,
+                          f"radix root: {label}, leaves={leaves}")

@@ -162,3 +162,34 @@ def test_device_requests_mixed_with_host_requests(binned_min_keys):
         assert np.array_equal(got, want[:cap])
     assert srv.stats.requests_done == len(reqs)
     srv.close()
+
+
+def test_native_replay_driver():
+    """lj_server_replay submits device requests from a native thread (all at
+    once, then at spaced arrival times) and returns every result; each equals
+    the oracle's."""
+    import torch
+    ws, ixs = _indexes()
+    reqs = _requests(ws, 50, seed=31)
+    srv = lj.Server(ixs, lj.lj_server_default_config(1 << 28))
+    items, outs = [], []
+    for i, S, want, cap, out in reqs:
+        s_dev = lj.to_device_keys(S)
+        o_dev = torch.full((max(cap, 1), 2), -1, dtype=torch.int32, device="cuda")
+        items.append((i, s_dev, o_dev if cap else None))
+        outs.append(o_dev)
+    torch.cuda.synchronize()
+    for arrival in (None, np.arange(len(items)) * 200_000):
+        print(f"[server] replay arrival={'none' if arrival is None else 'spaced'}", flush=True)
+        for o in outs:
+            o.fill_(-1)
+        torch.cuda.synchronize()
+        res = srv.replay(items, arrival)
+        for (i, S, want, cap, out), r, o in zip(reqs, res, outs):
+            assert r.count == len(want)
+            assert r.status == (lj.LJ_OK if cap >= len(want) else lj.LJ_ERR_CAPACITY)
+            got = o[:min(cap, len(want))].cpu().numpy().view(np.uint32)
+            assert np.array_equal(got, want[:cap])
+            assert r.done_ns >= r.start_ns >= r.submit_ns
+    assert srv.stats.requests_done == 2 * len(items)
+    srv.close()
