@@ -630,6 +630,13 @@ def bench_serving(args) -> None:
     served = lj.lj_server_default_config(24 << 30)
     served_binned = lj.lj_server_default_config(24 << 30)
     served_binned.binned_min_keys = 1 << 20
+    for c in (served, served_binned):
+        if args.serve_slots:
+            c.slots = args.serve_slots
+        if args.serve_batch_requests:
+            c.max_batch_requests = args.serve_batch_requests
+        if args.serve_batch_keys:
+            c.max_batch_keys = args.serve_batch_keys
     configs = [("plain_per_request", plain), ("served", served),
                ("served_binned", served_binned)]
 
@@ -700,6 +707,8 @@ def bench_serving(args) -> None:
                    "leaf_model": "fp32", "root": args.root,
                    "request_keys": "log-uniform 256..4194304", "requests_per_load": nreq,
                    "request_buffers": args.request_buffers, "server": best,
+                   "slots": int(served.slots), "max_batch_requests": int(served.max_batch_requests),
+                   "max_batch_keys": int(served.max_batch_keys),
                    "driver": args.driver if on_device else "python"},
         "saturation": {**{f"{n}_probes_per_s": keys_sat / sat[n][0] for n, _ in configs},
                        "served_max_batch": int(st_sat.max_batch_size),
@@ -972,6 +981,12 @@ def main():
     ap.add_argument("--request-buffers", choices=["host", "device"], default="device",
                     help="serving workload: request keys and pairs already in device "
                          "memory, or in pinned host memory (copied over PCIe)")
+    ap.add_argument("--serve-slots", type=int, default=0,
+                    help="serving workload: batches in flight (0 = the library default)")
+    ap.add_argument("--serve-batch-requests", type=int, default=0,
+                    help="serving workload: requests per batch (0 = the library default)")
+    ap.add_argument("--serve-batch-keys", type=int, default=0,
+                    help="serving workload: outer keys per batch (0 = the library default)")
     ap.add_argument("--driver", choices=["native", "python"], default="native",
                     help="serving workload with device buffers: requests submitted by the "
                          "library's native load driver, or one by one from Python threads")
