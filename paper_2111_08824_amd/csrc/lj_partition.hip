@@ -118,6 +118,50 @@ __global__ __launch_bounds__(kBlock) void bin_hist_kernel(const uint64_t* __rest
     }
 }
 
+// bin_hist_kernel<true> for an index with a radix root and at least kBins
+// leaves: a key's bin is its leaf scaled to kBins ranges, leaf * kBins / L
+// (the radix root gives leaves of about n / L keys each, so these ranges are
+// about equi-depth, like the fences; any bin order gives the same pairs).
+// The root's table is staged in LDS; no fence search.
+__global__ __launch_bounds__(kBlock) void bin_hist_root_kernel(const uint64_t* __restrict__ keys,
+                                                               RootModel root,
+                                                               uint16_t* __restrict__ bins,
+                                                               uint64_t m, uint32_t nchunks,
+                                                               uint32_t* __restrict__ hist) {
+    __shared__ __align__(16) uint32_t s_root[kRootTabLen];
+    __shared__ uint32_t cnt[kDigits];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    {
+        const uint4* src = (const uint4*)root.tab_dev;
+        uint4* dst = (uint4*)s_root;
+        for (uint32_t i = tid; i < kRootTabLen / 4; i += kBlock) dst[i] = src[i];
+    }
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        if (tid < (int)kDigits) cnt[tid] = 0;
+        __syncthreads();
+        const uint64_t e0 = (uint64_t)c * kPartChunk + (uint64_t)wave * kWaveSpan + lane;
+        uint64_t x[kPartItems];
+#pragma unroll
+        for (int k = 0; k < (int)kPartItems; ++k) {
+            const uint64_t p = e0 + (uint64_t)k * 64;
+            x[k] = keys[p < m ? p : m - 1];
+        }
+#pragma unroll
+        for (int k = 0; k < (int)kPartItems; ++k) {
+            const uint64_t p = e0 + (uint64_t)k * 64;
+            const uint32_t leaf = route_radix(root, s_root, x[k]);
+            const uint32_t b = (uint32_t)(((uint64_t)leaf * kBins) / root.leaves);
+            if (p < m) {
+                bins[p] = (uint16_t)b;
+                atomicAdd(&cnt[digit_of(b, 0)], 1u);
+            }
+        }
+        __syncthreads();
+        if (tid < (int)kDigits) hist[(uint64_t)tid * nchunks + c] = cnt[tid];
+        __syncthreads();
+    }
+}
+
 // In-place exclusive prefix sum of n counts (total < 2^62, and < 2^32 for
 // u32), one tile of kScanTile per block, tiles chained by decoupled
 // look-back.
@@ -345,9 +389,13 @@ hipError_t launch_partition(const lj_index* idx, const uint64_t* s, uint64_t m, 
     uint32_t* ctr = (uint32_t*)(w + L.scan_ctr);
 
     // Pass 1: low digit.
-    hipLaunchKernelGGL(bin_hist_kernel<true>, dim3(chunk_grid(nchunks, 2048)), dim3(kBlock), 0,
-                       stream, s, idx->fences_dev, idx->bucket_lo_dev, bins_s, m, nchunks, 0u,
-                       hist1);
+    if (idx->root.kind == kRootRadix && idx->leaves >= kBins)
+        hipLaunchKernelGGL(bin_hist_root_kernel, dim3(chunk_grid(nchunks, 2048)), dim3(kBlock), 0,
+                           stream, s, idx->root, bins_s, m, nchunks, hist1);
+    else
+        hipLaunchKernelGGL(bin_hist_kernel<true>, dim3(chunk_grid(nchunks, 2048)), dim3(kBlock),
+                           0, stream, s, idx->fences_dev, idx->bucket_lo_dev, bins_s, m, nchunks,
+                           0u, hist1);
     hipLaunchKernelGGL(scan_kernel<uint32_t>, dim3(scan_grid), dim3(kBlock), 0, stream, hist1,
                        nh, (uint64_t*)(w + L.scan_st1), ctr, err);
     hipLaunchKernelGGL(bin_scatter_kernel, dim3(chunk_grid(nchunks, 65535)), dim3(kBlock), 0,
