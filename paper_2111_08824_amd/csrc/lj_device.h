@@ -61,7 +61,7 @@ __device__ uint64_t look_back(uint64_t* status, uint32_t tile, uint64_t total,
                 // A predecessor never published: report and stop waiting so
                 // that the kernel still exits.
                 if ((st >> 62) == 0) {
-                    atomicOr(err, 1u);
+                    __hip_atomic_fetch_or(err, 1u, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
                     st = kFlagInc;
                 }
             }

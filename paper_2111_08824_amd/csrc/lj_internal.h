@@ -155,13 +155,18 @@ constexpr int kMinTile = kBlock * 4;  // smallest tile any launch uses
 
 // Workspace of a single probe: a 256-byte header followed by one status
 // word per tile.
+// The two counters every tile updates sit on separate cache lines: the
+// device serialises updates of one line.
 struct WsHeader {
     uint32_t tile_counter;  // dynamic tile ids
-    uint32_t done_counter;  // tiles finished
     uint32_t err;           // non-zero: a wait bound was hit
     uint32_t queue_count;   // binned probe of a gapped index: keys queued for the second pass
+    uint32_t pad0;
     uint64_t count;         // total pairs (internal count slot)
+    uint8_t pad1[128 - 24];
+    uint32_t done_counter;  // tiles finished
 };
+static_assert(sizeof(WsHeader) <= 256, "header fits its 256 bytes");
 constexpr uint64_t kWsHeaderBytes = 256;
 
 inline uint64_t num_tiles(uint64_t m, uint64_t tile) { return (m + tile - 1) / tile; }
@@ -200,10 +205,12 @@ __host__ __device__ inline uint32_t key_bucket(uint64_t x) {
 }
 
 // Byte offsets inside the workspace of a binned probe.  [0, ctrl_bytes) is
-// zeroed before every probe: the header (error flag, count), three scan
-// tile counters, the scans' status words and the per-chunk pair counts.
-// res2/res1/res0 (per-key results in bin, pass-1 and S order) reuse p1, p2
-// and p1 once those are dead.
+// zeroed before every probe: the header (error flag), the counter block
+// (scan tile counters in words 0-1, the emission's tile counter in word 2
+// and its done counter in word 32, a cache line further), the scans'
+// status words and one word per chunk of S (the emission's look-back
+// words; the sort join keeps per-chunk pair counts there).  res2/res1 (per-key results
+// in bin and pass-1 order) reuse p1 and p2 once those are dead.
 struct BinnedWs {
     uint64_t scan_ctr, scan_st1, scan_st2, scan_st3, counts, ctrl_bytes;
     uint64_t hist1, hist2, bins_s, bins_1, p1, p2, dest1, dest2, total;

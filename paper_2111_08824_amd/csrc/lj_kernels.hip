@@ -103,16 +103,25 @@ struct TileShared {
 };
 
 // Last tile of a batch to finish writes the batch's total (or UINT64_MAX
-// after a wait error).
+// after a wait error).  No fence orders a tile's status word before its
+// count of finished tiles (an agent-scope fence writes back the whole L2
+// and cost more than the rest of a short tile); instead the last tile to
+// finish waits until the inclusive prefix of the batch's last tile is
+// visible.  Every tile stored its inclusive prefix before counting itself
+// as done, so the wait ends; a wait error was flagged with a sequentially
+// consistent update before the flagging tile counted itself.
 __device__ void finish_tile(const TileJob& j) {
     if (threadIdx.x == 0) {
-        __threadfence();
         uint32_t done = atomicAdd(j.done, 1u);
         if (done == j.ntiles - 1) {
-            __threadfence();
+            const uint64_t* last = &j.status[j.ntiles - 1];
+            uint64_t st = ld_status(last);
+            for (uint32_t spins = 0; (st >> 62) != 2 && spins < kSpinLimit; ++spins) {
+                __builtin_amdgcn_s_sleep(1);
+                st = ld_status(last);
+            }
             uint32_t e = __hip_atomic_load(j.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            uint64_t tot = ld_status(&j.status[j.ntiles - 1]) & kValMask;
-            *j.count_out = e ? ~0ull : tot;
+            *j.count_out = e || (st >> 62) != 2 ? ~0ull : st & kValMask;
             // The count may live in pinned host memory (serving loop).
             __threadfence_system();
         }
@@ -593,15 +602,12 @@ __device__ __forceinline__ void search_keys_hash(const HBucket* __restrict__ buc
 
 // Steps 5-7 for one tile whose lower bounds and run lengths are known:
 // offsets, look-back, pair emission; then the tile is counted as done.
-// Without kLookBack the tile's output offset is given (excl_given) and the
-// batch total is written elsewhere.
-template <bool kUnique, int kItems, bool kWithOffsets, bool kLookBack = true>
+template <bool kUnique, int kItems, bool kWithOffsets>
 __device__ __forceinline__ void emit_tile(const TileJob& j, const uint32_t tile,
                                           const uint32_t kpl,
                                           TileShared<kItems, kWithOffsets>& sh,
                                           const uint32_t (&first)[kItems],
-                                          const uint32_t (&c)[kItems],
-                                          const uint64_t excl_given = 0) {
+                                          const uint32_t (&c)[kItems]) {
     static_assert(kUnique || kWithOffsets, "the duplicate path needs LDS offsets");
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -622,13 +628,9 @@ __device__ __forceinline__ void emit_tile(const TileJob& j, const uint32_t tile,
 #pragma unroll
         for (int q = 0; q < kItems * (kBlock / 64); ++q) total += sh.wsum[q];
         // 6: look-back.
-        if constexpr (kLookBack) {
-            if (wave == 0) {
-                uint64_t e = look_back(j.status, tile, total, j.err, lane);
-                if (lane == 0) sh.excl = e;
-            }
-        } else {
-            if (tid == 0) sh.excl = excl_given;
+        if (wave == 0) {
+            uint64_t e = look_back(j.status, tile, total, j.err, lane);
+            if (lane == 0) sh.excl = e;
         }
         __syncthreads();
         const uint64_t excl = sh.excl;
@@ -680,13 +682,9 @@ __device__ __forceinline__ void emit_tile(const TileJob& j, const uint32_t tile,
         for (int i = 0; i < kItems; ++i) sh.off[tid * kItems + i] = texcl + loc[i];
         if (tid == 0) sh.off[(kBlock * kItems)] = total;
         // 6: look-back.
-        if constexpr (kLookBack) {
-            if (wave == 0) {
-                uint64_t e = look_back(j.status, tile, total, j.err, lane);
-                if (lane == 0) sh.excl = e;
-            }
-        } else {
-            if (tid == 0) sh.excl = excl_given;
+        if (wave == 0) {
+            uint64_t e = look_back(j.status, tile, total, j.err, lane);
+            if (lane == 0) sh.excl = e;
         }
         __syncthreads();
         const uint64_t excl = sh.excl;
@@ -709,7 +707,7 @@ __device__ __forceinline__ void emit_tile(const TileJob& j, const uint32_t tile,
         }
     }
     __syncthreads();  // the block's LDS is reused by the next tile
-    if constexpr (kLookBack) finish_tile(j);
+    finish_tile(j);
 }
 
 // Last-mile search of a launch: binary or exponential search of R within
@@ -920,39 +918,49 @@ __global__ __launch_bounds__(kBlock) void gapped_queue_kernel(const GSlot* __res
     }
 }
 
-// Emission kernel of the binned probe: per-key results in S order (layout
-// of probe_binned_kernel), one chunk of kPartChunk keys per block, the
-// chunk's output offset from the scanned per-chunk pair counts -> steps 5
-// and 7 of the fused probe, with no wait on other blocks.
-template <bool kUnique>
-__global__ __launch_bounds__(kBlock) void emit_chunks_kernel(TileJob j, const void* res,
-                                                             const uint64_t* offs) {
-    constexpr int kItems = (int)kPartItems;
+// Last stage of the binned probe: puts the per-key results back in S order
+// and emits the pairs in one pass.  res holds the results in pass-1 order
+// (layout of probe_binned_kernel after the pass-2 gather); key p of S reads
+// res[dest[p]], where dest[p] is its pass-1 position.  Tiles of kBlock *
+// kItems keys of S, tile ids from an atomic counter, output offsets by
+// decoupled look-back over the tiles -> steps 5-7 of the probe without
+// writing the S-order results out and reading them back.  The tiles are
+// larger than a partition chunk because every tile costs two updates of
+// single counters, which the device serialises.
+template <bool kUnique, int kItems>
+__global__ __launch_bounds__(kBlock) void restore_emit_kernel(TileJob j,
+                                                              const uint32_t* __restrict__ dest,
+                                                              const void* __restrict__ res,
+                                                              uint32_t* tile_counter) {
+    __shared__ uint32_t s_tile;
     __shared__ TileShared<kItems, !kUnique> sh;
-    const uint32_t tile = blockIdx.x;
-    const uint64_t tbase = (uint64_t)tile * kPartChunk;
+    if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint64_t tbase = (uint64_t)tile * kBlock * kItems;
     uint32_t first[kItems], c[kItems];
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const uint64_t q = tbase + (uint64_t)k * kBlock + threadIdx.x;
+        first[k] = q < j.m ? dest[q] : ~0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const uint32_t d = first[k];
         if constexpr (kUnique) {
-            const uint32_t v = q < j.m ? ((const uint32_t*)res)[q] : ~0u;
+            const uint32_t v = d != ~0u ? ((const uint32_t*)res)[d] : ~0u;
             first[k] = v;
             c[k] = v != ~0u ? 1u : 0u;
         } else {
-            const uint64_t v = q < j.m ? ((const uint64_t*)res)[q] : 0ull;
+            const uint64_t v = d != ~0u ? ((const uint64_t*)res)[d] : 0ull;
             first[k] = (uint32_t)v;
             c[k] = (uint32_t)(v >> 32);
         }
     }
-    emit_tile<kUnique, kItems, !kUnique, false>(j, tile, kItems, sh, first, c, offs[tile]);
+    emit_tile<kUnique, kItems, !kUnique>(j, tile, kItems, sh, first, c);
 }
-
-// Total of the binned probe, or UINT64_MAX after a wait error.
-__global__ void finish_binned_kernel(const uint64_t* total, const uint32_t* err,
-                                     uint64_t* count_out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *count_out = *err ? ~0ull : *total;
-}
+constexpr int kItemsRestore = 32;     // unique R
+constexpr int kItemsRestoreDup = 16;  // duplicates: LDS offsets per key
 
 __global__ void zero_words(uint64_t* w, uint64_t nwords) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
@@ -1339,10 +1347,9 @@ hipError_t launch_probe_binned(const lj_index* idx, const uint64_t* s, uint64_t 
     if (e != hipSuccess) return e;
     e = launch_partition(idx, s, m, ws, L, stream);
     if (e != hipSuccess) return e;
-    // res2 (bin order) in p1, res1 (pass-1 order) in p2, res0 (S order) in p1.
+    // res2 (bin order) in p1, res1 (pass-1 order) in p2.
     void* res2 = w + L.p1;
     void* res1 = w + L.p2;
-    void* res0 = w + L.p1;
     const uint64_t* keys = (const uint64_t*)(w + L.p2);
     if (ev0) {
         e = hipEventRecord(ev0, stream);
@@ -1365,31 +1372,32 @@ hipError_t launch_probe_binned(const lj_index* idx, const uint64_t* s, uint64_t 
         if (e != hipSuccess) return e;
     }
     e = launch_unpermute((const uint32_t*)(w + L.dest2), res2, res1, m, dup, stream);
-    if (e == hipSuccess)
-        e = launch_unpermute_count((const uint32_t*)(w + L.dest1), res1, res0, m, dup, ws, L,
-                                   stream);
     if (e != hipSuccess) return e;
 
-    const uint64_t* offs = (const uint64_t*)(w + L.counts);
+    // Chunk ids, finished chunks and per-chunk look-back words live in the
+    // zeroed control block.
     WsHeader* hdr = (WsHeader*)ws;
+    uint32_t* ctr = (uint32_t*)(w + L.scan_ctr);
     TileJob j{};
     j.s = s;
     j.m = m;
     j.out = out;
     j.cap = out ? cap : 0;
     j.count_out = count_dev;
+    j.status = (uint64_t*)(w + L.counts);  // nchunks + 1 words >= tiles
+    j.done = ctr + 32;                     // a cache line apart from the tile counter
     j.err = &hdr->err;
-    j.ntiles = (uint32_t)num_tiles(m, kPartChunk);
     j.kind = kind;
-    j.kpl = kPartItems;
+    j.kpl = dup ? kItemsRestoreDup : kItemsRestore;
+    j.ntiles = (uint32_t)num_tiles(m, (uint64_t)kBlock * j.kpl);
     if (dup)
-        hipLaunchKernelGGL(emit_chunks_kernel<false>, dim3(j.ntiles), dim3(kBlock), 0, stream, j,
-                           (const void*)res0, offs);
+        hipLaunchKernelGGL((restore_emit_kernel<false, kItemsRestoreDup>), dim3(j.ntiles),
+                           dim3(kBlock), 0, stream, j, (const uint32_t*)(w + L.dest1),
+                           (const void*)res1, ctr + 2);
     else
-        hipLaunchKernelGGL(emit_chunks_kernel<true>, dim3(j.ntiles), dim3(kBlock), 0, stream, j,
-                           (const void*)res0, offs);
-    hipLaunchKernelGGL(finish_binned_kernel, dim3(1), dim3(64), 0, stream, offs + j.ntiles,
-                       (const uint32_t*)&hdr->err, count_dev);
+        hipLaunchKernelGGL((restore_emit_kernel<true, kItemsRestore>), dim3(j.ntiles),
+                           dim3(kBlock), 0, stream, j, (const uint32_t*)(w + L.dest1),
+                           (const void*)res1, ctr + 2);
     return hipGetLastError();
 }
 
