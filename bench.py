@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "outer-key probes/sec + achieved HBM GB/s vs roofline; p50/p99 probe latency"
 HBM_PEAK_GBS = 8000.0
 PROBE_KERNEL_SOURCES = ["paper_2111_08824_amd/csrc/lj_kernels.hip",
+                        "paper_2111_08824_amd/csrc/lj_partition.hip",
                         "paper_2111_08824_amd/csrc/lj_device.h",
                         "paper_2111_08824_amd/csrc/rmi_eval.h",
                         "paper_2111_08824_amd/csrc/lj_internal.h"]
@@ -517,9 +518,15 @@ def bench_serving(args) -> None:
 
     t0 = time.perf_counter()
     ws = workloads.resident_indexes()
-    ixs = [lj.lj_build_rmi(w.R, w.leaves, lj.LJ_LEAF_FP32 | root_flag(args)) for w in ws]
-    print(f"[bench] 8 resident indexes ready ({time.perf_counter() - t0:.1f} s)",
-          file=sys.stderr, flush=True)
+    flags = lj.LJ_LEAF_FP32 | root_flag(args)
+    if args.index == "gapped":
+        ixs = [lj.lj_build_gapped_rmi(w.R, w.leaves, args.slots_per_key, flags) for w in ws]
+    elif args.index == "hash":
+        ixs = [lj.lj_build_learned_hash(w.R, w.leaves, args.slots_per_key, flags) for w in ws]
+    else:
+        ixs = [lj.lj_build_rmi(w.R, w.leaves, flags) for w in ws]
+    print(f"[bench] 8 resident indexes ready ({args.index}, "
+          f"{time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
     rng = np.random.default_rng(7)
     max_m = 4 << 20
     nreq = args.requests
@@ -637,6 +644,9 @@ def bench_serving(args) -> None:
             c.max_batch_requests = args.serve_batch_requests
         if args.serve_batch_keys:
             c.max_batch_keys = args.serve_batch_keys
+    if args.serve_kpl:
+        for c in (plain, served, served_binned):
+            c.keys_per_lane[:] = [int(v) for v in args.serve_kpl.split(",")]
     configs = [("plain_per_request", plain), ("served", served),
                ("served_binned", served_binned)]
 
@@ -704,11 +714,12 @@ def bench_serving(args) -> None:
         "ms_per_step": round(w_served * 1e3 / len(sat_reqs), 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "serving-8x50M", "indexes": 8, "inner_keys_each": 50_000_000,
-                   "leaf_model": "fp32", "root": args.root,
+                   "index": args.index, "leaf_model": "fp32", "root": args.root,
                    "request_keys": "log-uniform 256..4194304", "requests_per_load": nreq,
                    "request_buffers": args.request_buffers, "server": best,
                    "slots": int(served.slots), "max_batch_requests": int(served.max_batch_requests),
                    "max_batch_keys": int(served.max_batch_keys),
+                   "keys_per_lane": [int(v) for v in served.keys_per_lane],
                    "driver": args.driver if on_device else "python"},
         "saturation": {**{f"{n}_probes_per_s": keys_sat / sat[n][0] for n, _ in configs},
                        "served_max_batch": int(st_sat.max_batch_size),
@@ -987,6 +998,9 @@ def main():
                     help="serving workload: requests per batch (0 = the library default)")
     ap.add_argument("--serve-batch-keys", type=int, default=0,
                     help="serving workload: outer keys per batch (0 = the library default)")
+    ap.add_argument("--serve-kpl", default="",
+                    help="serving workload: keys per lane of the four request size classes, "
+                         "e.g. 4,8,8,8 (empty = the library default)")
     ap.add_argument("--driver", choices=["native", "python"], default="native",
                     help="serving workload with device buffers: requests submitted by the "
                          "library's native load driver, or one by one from Python threads")

@@ -275,7 +275,8 @@ typedef struct {
  * Launch shape of a plan.  Batches fall in four size classes
  * (m < 2^13, < 2^17, < 2^21, larger); a class's tiles hold
  * 256 * keys_per_lane[class] outer keys, with keys_per_lane in
- * {4, 8, 16, 24} (24 is lowered to 16 for indexes with duplicate keys).
+ * {4, 8, 16, 24} (24 is lowered to 16 for indexes with duplicate keys);
+ * the default is {4, 8, 8, 8}.
  * `branches` (1..16) is the number of parallel streams the batches are
  * spread over; `use_graph` selects graph replay (1) or direct launches (0).
  * `binned_min_keys`: batches of at least this many outer keys use the

@@ -63,8 +63,8 @@ int size_class(uint64_t m) {
 void default_tuning(lj_batch_tuning* t) {
     t->keys_per_lane[0] = 4;
     t->keys_per_lane[1] = 8;
-    t->keys_per_lane[2] = 16;
-    t->keys_per_lane[3] = 24;
+    t->keys_per_lane[2] = 8;
+    t->keys_per_lane[3] = 8;
     t->branches = 4;
     t->use_graph = 1;
     t->binned_min_keys = 0;
@@ -101,7 +101,7 @@ int batch_mode(const lj_batch_tuning& t, uint64_t m) {
 hipError_t enqueue_one(const lj_batch_desc& d, void* ws, uint32_t kpl, int mode,
                        hipStream_t st) {
     if (d.m == 0) return launch_set_u64(d.out_count_dev, 0, st);
-    if (d.index->max_mult > 1) kpl = std::min<uint32_t>(kpl, kItemsDup);
+    if (d.index->max_mult > 1) kpl = std::min<uint32_t>(kpl, kItemsDupMax);
     return launch_probe(d.index, d.s_keys_dev, d.m, d.out_pairs_dev,
                         d.out_pairs_dev ? d.out_capacity : 0, d.out_count_dev, ws, st, nullptr,
                         nullptr, kpl, mode);

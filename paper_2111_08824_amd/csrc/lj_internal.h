@@ -135,17 +135,19 @@ __host__ __device__ inline uint64_t gapped_pred(const Leaf& lf, uint64_t x, uint
 }
 
 // Tile geometry of the fused probe kernel: kBlock threads, each holding
-// kItems outer keys (kItemsUnique when R has no duplicate keys, kItemsDup
-// otherwise, where the run scan and the LDS offsets need more room;
-// kItemsGapped on a gapped index without duplicates, whose search state
-// needs more registers).
+// kItems outer keys.  Defaults: kItemsUnique when R has no duplicate keys,
+// kItemsDup otherwise (at most kItemsDupMax: the LDS offsets per key),
+// kItemsGapped on a gapped index, kItemsHash on a learned hash index; the
+// shallowest depths that still keep enough loads in flight measured
+// fastest.
 constexpr int kBlock = 256;
 constexpr uint32_t kLineKeys = 16;  // keys of R per 128-byte cache line (line samples)
 // The direct probe searches in two stages when the index's mean window is at
 // least this long (the binned probe always does).
 constexpr double kTwoStageMinWindow = 64.0;
-constexpr int kItemsUnique = 24;
-constexpr int kItemsDup = 16;
+constexpr int kItemsUnique = 8;
+constexpr int kItemsDup = 4;      // default with duplicates
+constexpr int kItemsDupMax = 16;  // largest with duplicates (LDS offsets per key)
 constexpr int kItemsGapped = 8;
 constexpr int kItemsHash = 8;  // learned hash index: a 64-byte bucket in flight per key
 constexpr int kItemsBinned = 16;  // search kernel of the binned probe (measured best)

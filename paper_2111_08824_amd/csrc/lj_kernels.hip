@@ -1219,18 +1219,22 @@ hipError_t launch_probe_items(const TileJob& j, uint32_t* ctr, hipStream_t strea
                                    block, 0, stream, j, ctr);
                 break;
             case kJobDup:
-                if constexpr (kItems <= kItemsDup)
+                if constexpr (kItems <= kItemsDupMax)
                     hipLaunchKernelGGL((probe_join_kernel<LeafF32, false, kItems, kSearch>),
                                        grid, block, 0, stream, j, ctr);
+                else
+                    return hipErrorInvalidValue;
                 break;
             case kJobFp64:
                 hipLaunchKernelGGL((probe_join_kernel<LeafF64, true, kItems, kSearch>), grid,
                                    block, 0, stream, j, ctr);
                 break;
             default:
-                if constexpr (kItems <= kItemsDup)
+                if constexpr (kItems <= kItemsDupMax)
                     hipLaunchKernelGGL((probe_join_kernel<LeafF64, false, kItems, kSearch>),
                                        grid, block, 0, stream, j, ctr);
+                else
+                    return hipErrorInvalidValue;
                 break;
         }
         return hipGetLastError();

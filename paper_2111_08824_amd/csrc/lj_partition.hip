@@ -41,6 +41,19 @@ __device__ inline uint32_t digit_of(uint32_t bin, uint32_t shift) {
     return (bin >> shift) & (kDigits - 1);
 }
 
+// Lane d's count of the valid elements of its wave whose digit is d: six
+// ballots on the digit's bits select the lanes that match d.  Counting this
+// way needs no LDS atomics (which conflict heavily on 64 counters).
+__device__ __forceinline__ uint32_t digit_match_count(uint32_t dg, bool valid, int lane) {
+    uint64_t mine = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < (int)kDigitBits; ++bit) {
+        const uint64_t bb = __ballot((dg >> bit) & 1u);
+        mine &= ((lane >> bit) & 1) ? bb : ~bb;
+    }
+    return (uint32_t)__popcll(mine);
+}
+
 // Per chunk: digit histogram into hist[digit * nchunks + chunk].  With
 // kFromKeys the bins are computed from the keys and stored to `bins`;
 // otherwise they are read from `bins`.  A key's bin is the number of fences
@@ -57,6 +70,7 @@ __global__ __launch_bounds__(kBlock) void bin_hist_kernel(const uint64_t* __rest
     __shared__ uint64_t sf[kFromKeys ? kBins : 1];
     __shared__ uint16_t sb[kFromKeys ? kBuckets + 2 : 2];
     __shared__ uint32_t cnt[kDigits];
+    __shared__ uint32_t wcnt[kFromKeys ? 1 : kWaves][kDigits];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if constexpr (kFromKeys) {
         for (uint32_t i = tid; i < kBins - 1; i += kBlock) sf[i] = fences[i];
@@ -109,22 +123,39 @@ __global__ __launch_bounds__(kBlock) void bin_hist_kernel(const uint64_t* __rest
                 b[k] = p < m ? bins[p] : 0u;
             }
         }
+        if constexpr (kFromKeys) {
 #pragma unroll
-        for (int k = 0; k < (int)kPartItems; ++k)
-            if (e0 + (uint64_t)k * 64 < m) atomicAdd(&cnt[digit_of(b[k], shift)], 1u);
-        __syncthreads();
-        if (tid < (int)kDigits) hist[(uint64_t)tid * nchunks + c] = cnt[tid];
+            for (int k = 0; k < (int)kPartItems; ++k)
+                if (e0 + (uint64_t)k * 64 < m) atomicAdd(&cnt[digit_of(b[k], shift)], 1u);
+            __syncthreads();
+            if (tid < (int)kDigits) hist[(uint64_t)tid * nchunks + c] = cnt[tid];
+        } else {
+            uint32_t run = 0;
+#pragma unroll
+            for (int k = 0; k < (int)kPartItems; ++k)
+                run += digit_match_count(digit_of(b[k], shift), e0 + (uint64_t)k * 64 < m, lane);
+            wcnt[wave][lane] = run;
+            __syncthreads();
+            if (tid < (int)kDigits) {
+                uint32_t t = 0;
+#pragma unroll
+                for (int w = 0; w < kWaves; ++w) t += wcnt[w][tid];
+                hist[(uint64_t)tid * nchunks + c] = t;
+            }
+        }
         __syncthreads();
     }
 }
 
 // bin_hist_kernel<true> for an index with a radix root and at least kBins
-// leaves: a key's bin is its leaf scaled to kBins ranges, leaf * kBins / L
-// (the radix root gives leaves of about n / L keys each, so these ranges are
-// about equi-depth, like the fences; any bin order gives the same pairs).
-// The root's table is staged in LDS; no fence search.
+// leaves: a key's bin is its leaf scaled to kBins ranges,
+// (leaf * bin_mul) >> 32 with bin_mul = floor(kBins * 2^32 / L), so bin <
+// kBins and bins are non-decreasing in the key (the radix root gives leaves
+// of about n / L keys each, so these ranges are about equi-depth, like the
+// fences; any bin order gives the same pairs).  The root's table is staged
+// in LDS; no fence search.
 __global__ __launch_bounds__(kBlock) void bin_hist_root_kernel(const uint64_t* __restrict__ keys,
-                                                               RootModel root,
+                                                               RootModel root, uint64_t bin_mul,
                                                                uint16_t* __restrict__ bins,
                                                                uint64_t m, uint32_t nchunks,
                                                                uint32_t* __restrict__ hist) {
@@ -150,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void bin_hist_root_kernel(const uint64_t* _
         for (int k = 0; k < (int)kPartItems; ++k) {
             const uint64_t p = e0 + (uint64_t)k * 64;
             const uint32_t leaf = route_radix(root, s_root, x[k]);
-            const uint32_t b = (uint32_t)(((uint64_t)leaf * kBins) / root.leaves);
+            const uint32_t b = (uint32_t)(((uint64_t)leaf * bin_mul) >> 32);
             if (p < m) {
                 bins[p] = (uint16_t)b;
                 atomicAdd(&cnt[digit_of(b, 0)], 1u);
@@ -287,11 +318,11 @@ __global__ __launch_bounds__(kBlock) void bin_scatter_kernel(
         __syncthreads();
         const uint32_t nvalid = m - c0 < kPartChunk ? (uint32_t)(m - c0) : kPartChunk;
         for (uint32_t lp = tid; lp < nvalid; lp += kBlock) {
-            const uint32_t bn = sbin[lp];
-            const uint32_t dg = digit_of(bn, shift);
+            const uint32_t bin = sbin[lp];
+            const uint32_t dg = digit_of(bin, shift);
             const uint32_t dst = gstart[dg] + (lp - lstart[dg]);
             keys_out[dst] = skey[lp];
-            if (bins_out) bins_out[dst] = (uint16_t)bn;
+            if (bins_out) bins_out[dst] = (uint16_t)bin;
         }
         __syncthreads();
     }
@@ -391,7 +422,8 @@ hipError_t launch_partition(const lj_index* idx, const uint64_t* s, uint64_t m, 
     // Pass 1: low digit.
     if (idx->root.kind == kRootRadix && idx->leaves >= kBins)
         hipLaunchKernelGGL(bin_hist_root_kernel, dim3(chunk_grid(nchunks, 2048)), dim3(kBlock), 0,
-                           stream, s, idx->root, bins_s, m, nchunks, hist1);
+                           stream, s, idx->root, ((uint64_t)kBins << 32) / idx->root.leaves,
+                           bins_s, m, nchunks, hist1);
     else
         hipLaunchKernelGGL(bin_hist_kernel<true>, dim3(chunk_grid(nchunks, 2048)), dim3(kBlock),
                            0, stream, s, idx->fences_dev, idx->bucket_lo_dev, bins_s, m, nchunks,

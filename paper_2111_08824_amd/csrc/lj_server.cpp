@@ -361,8 +361,8 @@ void lj_server_default_config(lj_server_config* c, uint64_t budget_bytes) {
     c->max_batch_keys = 1ull << 22;
     c->keys_per_lane[0] = 4;
     c->keys_per_lane[1] = 8;
-    c->keys_per_lane[2] = 16;
-    c->keys_per_lane[3] = 24;
+    c->keys_per_lane[2] = 8;
+    c->keys_per_lane[3] = 8;
     c->binned_min_keys = 0;
     c->fused = 1;
 }

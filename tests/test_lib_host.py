@@ -85,7 +85,7 @@ def test_workspace_sizes():
 def test_default_batch_tuning_layout():
     # Filled by the library: a layout mismatch with lj.h shows as wrong fields.
     t = lj.lj_batch_default_tuning()
-    assert list(t.keys_per_lane) == [4, 8, 16, 24]
+    assert list(t.keys_per_lane) == [4, 8, 8, 8]
     assert (t.branches, t.use_graph, t.binned_min_keys, t.measured_ms) == (4, 1, 0, 0.0)
     assert ctypes.sizeof(lj.lj_batch_tuning) == 40
 
