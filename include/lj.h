@@ -282,11 +282,11 @@ typedef struct {
  * `binned_min_keys`: batches of at least this many outer keys use the
  * binned probe (LJ_PROBE_BINNED) and smaller ones the direct probe; 0 keeps
  * each index's own choice, UINT64_MAX probes every batch directly.
- * `fused` = 1: all batches probed directly on plain RMIs (binary search)
- * run in one kernel per leaf arithmetic and duplicate class (usually one
- * launch for the whole plan): the tiles of every batch share one tile-id
- * queue, each tile with its own batch's keys per lane (at most 16); 0: one
- * kernel per batch.  `measured_ms` is filled by lj_batch_autotune.
+ * `fused` = 1: all batches probed directly on plain RMIs (binary search) or
+ * gapped RMIs run in one kernel per index kind, leaf arithmetic and
+ * duplicate class (usually one launch for the whole plan): the tiles of
+ * every batch share one tile-id queue, each tile with its own batch's keys
+ * per lane (4 or 8: larger settings run as 8); 0: one kernel per batch.  `measured_ms` is filled by lj_batch_autotune.
  */
 typedef struct {
     uint32_t keys_per_lane[4];
@@ -344,7 +344,7 @@ int lj_batch_autotune(const lj_batch_desc* descs, uint32_t k, hipStream_t stream
  * soon as one of `slots` streams is free (so requests that arrive while
  * others run join the next batch), and enqueues the batch on that stream:
  * the key copies, then (with `fused`) one kernel per kernel group for all
- * requests probed directly on plain RMIs, which writes each
+ * requests probed directly on plain or gapped RMIs, which writes each
  * request's count straight into pinned host memory, then every other
  * request's probe and count copy; batches on different streams overlap on
  * the device and on the copy engines.  A completion thread per stream
@@ -363,9 +363,9 @@ typedef struct {
     uint64_t binned_min_keys;     /* requests of at least this many keys use the binned
                                      probe, smaller ones the direct probe; 0 keeps each
                                      index's own choice (LJ_PROBE_BINNED) */
-    uint32_t fused;               /* 1: a batch's direct probes on plain RMIs run in one
-                                     fused launch (see lj_batch_tuning); 0: one probe
-                                     kernel and count copy per request */
+    uint32_t fused;               /* 1: a batch's direct probes on plain or gapped RMIs
+                                     run in one fused launch (see lj_batch_tuning);
+                                     0: one probe kernel and count copy per request */
     uint32_t pad;
 } lj_server_config;
 
@@ -390,7 +390,7 @@ typedef struct {
 } lj_server_stats;
 
 /* Fill *config with defaults for a budget: 8 slots, 16 requests and 2^22
- * keys per batch, keys per lane 4/8/16/24, binned_min_keys 0, fused 1. */
+ * keys per batch, keys per lane 4/8/8/8, binned_min_keys 0, fused 1. */
 void lj_server_default_config(lj_server_config* config, uint64_t budget_bytes);
 
 /*

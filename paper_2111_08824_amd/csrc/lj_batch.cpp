@@ -182,7 +182,8 @@ int plan_create(const lj_batch_desc* descs, uint32_t k, const lj_batch_tuning* t
     p->kpl.assign(k, 0);
     p->mode.assign(k, 0);
     p->fused.assign(k, -1);
-    int slot_of_group[4] = {-1, -1, -1, -1};
+    int slot_of_group[lj::kFusedGroups];
+    std::fill(slot_of_group, slot_of_group + lj::kFusedGroups, -1);
     for (uint32_t b : order) {
         const lj_index* idx = descs[b].index;
         p->kpl[b] = t.keys_per_lane[lj::size_class(descs[b].m)];

@@ -151,7 +151,7 @@ constexpr int kItemsDupMax = 16;  // largest with duplicates (LDS offsets per ke
 constexpr int kItemsGapped = 8;
 constexpr int kItemsHash = 8;  // learned hash index: a 64-byte bucket in flight per key
 constexpr int kItemsBinned = 16;  // search kernel of the binned probe (measured best)
-constexpr int kItemsFused = 16;   // largest keys per lane of a fused launch
+constexpr int kItemsFused = 8;    // largest keys per lane of a fused launch
 constexpr int kSetupChunk = 4;
 constexpr int kMinTile = kBlock * 4;  // smallest tile any launch uses
 
@@ -322,12 +322,14 @@ inline uint64_t fused_job_ws_bytes(uint64_t m, uint32_t kpl) {
 // kpl: keys per lane of the launch (4, 8, 16 or, without duplicates, 24;
 // 0 = the default for the index).
 bool probe_kpl_supported(uint32_t kpl, bool dup);
-// Fused launches: the kernel group of an index (leaf arithmetic and
-// duplicates; -1 for index kinds a fused launch does not take: gapped, hash,
-// exponential search), the keys per lane a batch gets in it, one batch's
-// entry, and the launch itself (clears the header and every batch's
-// workspace first; jobs_dev in device memory, sorted by tile0, all of group
-// `group`).
+// Fused launches: the kernel group of an index (0..kFusedGroups-1: leaf
+// arithmetic, duplicates, plain or gapped RMI; -1 for index kinds a fused
+// launch does not take: learned hash, exponential search), the keys per
+// lane a batch gets in it, one batch's entry, and the launch itself (clears
+// the header and every batch's workspace first; jobs_dev in device memory,
+// sorted by tile0, all of group `group`).
+constexpr int kFusedGroupGapped = 4;  // + (kJobFp64 | kJobDup) bits
+constexpr int kFusedGroups = 8;
 int fused_group(const lj_index* idx);
 uint32_t fused_kpl(const lj_index* idx, uint32_t kpl);
 FusedJob make_fused_job(const lj_index* idx, const uint64_t* s, uint64_t m, lj_pair* out,

@@ -1112,11 +1112,11 @@ __global__ void predict_windows_kernel(const uint64_t* keys, uint64_t m, const L
 // new ones, which keeps every CU's slots filled the way a loop over tile
 // ids in long-lived blocks would; such a loop was tried and costs
 // registers (the compiler keeps loop-invariant constants of the tile shapes
-// live across iterations: 248-256 VGPRs, one wave per SIMD on unique R,
-// against 183 and two waves here).  A tile runs steps 1-7 of probe_tile with its batch's
-// own keys per lane (4, 8 or 16) and line-sample stage, using the LDS of
-// the largest tile shape.
-template <class Leaf, bool kUnique, int kItems, int kMaxItems>
+// live across iterations: 248-256 VGPRs, one wave per SIMD on unique R with
+// tiles of up to 16 keys per lane, against 183 and two waves here).  A tile
+// runs steps 1-7 of probe_tile with its batch's own keys per lane (4 or 8)
+// and line-sample stage, using the LDS of the largest tile shape.
+template <class Leaf, bool kUnique, int kItems, int kMaxItems, int kSearch>
 __device__ __forceinline__ void fused_tile(const TileJob& j, const uint32_t* rtab,
                                            const uint32_t tile, const bool two_stage,
                                            char* lds) {
@@ -1124,18 +1124,28 @@ __device__ __forceinline__ void fused_tile(const TileJob& j, const uint32_t* rta
     static_assert(sizeof(Sh) <= sizeof(TileShared<kMaxItems, !kUnique>), "LDS of a tile");
     Sh& sh = *reinterpret_cast<Sh*>(lds);
     uint32_t first[kItems], c[kItems];
-    search_keys<Leaf, kUnique, kItems, false>(j.r, j.rs, (const Leaf*)j.leaves, j.root, rtab,
-                                              j.s, j.m, (uint64_t)tile * kBlock * kItems, kItems,
-                                              first, c, two_stage);
+    const uint64_t tbase = (uint64_t)tile * kBlock * kItems;
+    if constexpr (kSearch == kSearchGapped)
+        search_keys_gapped<Leaf, kUnique, kItems>(j.slots, j.nslots, j.gap,
+                                                  (const Leaf*)j.leaves, j.root, rtab, j.s, j.m,
+                                                  tbase, kItems, first, c);
+    else
+        search_keys<Leaf, kUnique, kItems, false>(j.r, j.rs, (const Leaf*)j.leaves, j.root,
+                                                  rtab, j.s, j.m, tbase, kItems, first, c,
+                                                  two_stage);
     emit_tile<kUnique, kItems, !kUnique>(j, tile, kItems, sh, first, c);
 }
 
-template <class Leaf, bool kUnique>
+// kSearch: kSearchBinary (plain RMI; each batch's own line-sample stage) or
+// kSearchGapped (gapped RMI).  The kernel's registers are those of its
+// largest tile shape, so it offers at most kItemsFused (kItemsGapped) keys
+// per lane: deeper tiles would cut the waves per SIMD of every tile.
+template <class Leaf, bool kUnique, int kSearch>
 __global__ __launch_bounds__(kBlock) void probe_fused_kernel(const FusedJob* __restrict__ jobs,
                                                              uint32_t njobs,
                                                              uint32_t total_tiles,
                                                              uint32_t* tile_counter) {
-    constexpr int kMax = kItemsFused;
+    constexpr int kMax = kSearch == kSearchGapped ? kItemsGapped : kItemsFused;
     __shared__ __align__(16) char lds[sizeof(TileShared<kMax, !kUnique>)];
     __shared__ __align__(16) uint32_t s_root[kRootTabLen];
     __shared__ uint32_t s_tile, s_job;
@@ -1159,10 +1169,14 @@ __global__ __launch_bounds__(kBlock) void probe_fused_kernel(const FusedJob* __r
     __syncthreads();
     const uint32_t tile = t - jobs[b].tile0;
     const bool two = jobs[b].two_stage != 0;
-    switch (j.kpl) {
-        case 4: fused_tile<Leaf, kUnique, 4, kMax>(j, s_root, tile, two, lds); break;
-        case 8: fused_tile<Leaf, kUnique, 8, kMax>(j, s_root, tile, two, lds); break;
-        default: fused_tile<Leaf, kUnique, 16, kMax>(j, s_root, tile, two, lds); break;
+    static_assert(kMax == 8 || kMax == 16, "fused tiles: 4, 8 or 16 keys per lane");
+    if (j.kpl == 4) {
+        fused_tile<Leaf, kUnique, 4, kMax, kSearch>(j, s_root, tile, two, lds);
+    } else if constexpr (kMax == 16) {
+        if (j.kpl == 8) fused_tile<Leaf, kUnique, 8, kMax, kSearch>(j, s_root, tile, two, lds);
+        else fused_tile<Leaf, kUnique, 16, kMax, kSearch>(j, s_root, tile, two, lds);
+    } else {
+        fused_tile<Leaf, kUnique, 8, kMax, kSearch>(j, s_root, tile, two, lds);
     }
 }
 
@@ -1465,14 +1479,14 @@ hipError_t launch_probe(const lj_index* idx, const uint64_t* s, uint64_t m, lj_p
 
 int fused_group(const lj_index* idx) {
     const uint32_t kind = job_kind(idx);
-    if (kind & (kJobExp | kJobGapped | kJobHash)) return -1;
-    return (int)(kind & (kJobFp64 | kJobDup));
+    if (kind & (kJobExp | kJobHash)) return -1;
+    return (int)(kind & (kJobFp64 | kJobDup)) + ((kind & kJobGapped) ? kFusedGroupGapped : 0);
 }
 
 uint32_t fused_kpl(const lj_index* idx, uint32_t kpl) {
-    (void)idx;
-    if (kpl != 4 && kpl != 8 && kpl != 16 && kpl != 24) kpl = 16;
-    return kpl < (uint32_t)kItemsFused ? kpl : (uint32_t)kItemsFused;
+    if (kpl != 4 && kpl != 8 && kpl != 16 && kpl != 24) kpl = 8;
+    const uint32_t cap = idx->gap ? (uint32_t)kItemsGapped : (uint32_t)kItemsFused;
+    return kpl < cap ? kpl : cap;
 }
 
 FusedJob make_fused_job(const lj_index* idx, const uint64_t* s, uint64_t m, lj_pair* out,
@@ -1497,11 +1511,11 @@ FusedJob make_fused_job(const lj_index* idx, const uint64_t* s, uint64_t m, lj_p
 
 namespace {
 
-template <class Leaf, bool kUnique>
+template <class Leaf, bool kUnique, int kSearch>
 hipError_t launch_fused_typed(const FusedJob* jobs, uint32_t njobs, uint32_t total_tiles,
                               uint32_t* tile_counter, hipStream_t stream) {
-    hipLaunchKernelGGL((probe_fused_kernel<Leaf, kUnique>), dim3(total_tiles), dim3(kBlock), 0,
-                       stream, jobs, njobs, total_tiles, tile_counter);
+    hipLaunchKernelGGL((probe_fused_kernel<Leaf, kUnique, kSearch>), dim3(total_tiles),
+                       dim3(kBlock), 0, stream, jobs, njobs, total_tiles, tile_counter);
     return hipGetLastError();
 }
 
@@ -1515,14 +1529,24 @@ hipError_t launch_probe_fused(const FusedJob* jobs_dev, uint32_t njobs, uint32_t
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     uint32_t* ctr = hdr;
+    constexpr int kB = kSearchBinary, kG = kSearchGapped, kGg = kFusedGroupGapped;
     switch (group) {
-        case 0: return launch_fused_typed<LeafF32, true>(jobs_dev, njobs, total_tiles, ctr, stream);
+        case 0:
+            return launch_fused_typed<LeafF32, true, kB>(jobs_dev, njobs, total_tiles, ctr, stream);
         case kJobDup:
-            return launch_fused_typed<LeafF32, false>(jobs_dev, njobs, total_tiles, ctr, stream);
+            return launch_fused_typed<LeafF32, false, kB>(jobs_dev, njobs, total_tiles, ctr, stream);
         case kJobFp64:
-            return launch_fused_typed<LeafF64, true>(jobs_dev, njobs, total_tiles, ctr, stream);
+            return launch_fused_typed<LeafF64, true, kB>(jobs_dev, njobs, total_tiles, ctr, stream);
         case kJobFp64 | kJobDup:
-            return launch_fused_typed<LeafF64, false>(jobs_dev, njobs, total_tiles, ctr, stream);
+            return launch_fused_typed<LeafF64, false, kB>(jobs_dev, njobs, total_tiles, ctr, stream);
+        case kGg:
+            return launch_fused_typed<LeafF32, true, kG>(jobs_dev, njobs, total_tiles, ctr, stream);
+        case kGg + kJobDup:
+            return launch_fused_typed<LeafF32, false, kG>(jobs_dev, njobs, total_tiles, ctr, stream);
+        case kGg + kJobFp64:
+            return launch_fused_typed<LeafF64, true, kG>(jobs_dev, njobs, total_tiles, ctr, stream);
+        case kGg + (kJobFp64 | kJobDup):
+            return launch_fused_typed<LeafF64, false, kG>(jobs_dev, njobs, total_tiles, ctr, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -122,7 +122,7 @@ struct lj_server {
     void schedule_loop();
     void slot_loop(Slot* s);
     hipError_t enqueue_batch(Slot* s);
-    uint32_t grp_tiles_[4] = {0, 0, 0, 0};  // scratch of enqueue_batch (scheduler thread)
+    uint32_t grp_tiles_[lj::kFusedGroups] = {};  // scratch of enqueue_batch (scheduler thread)
 };
 
 namespace {
@@ -155,12 +155,13 @@ uint64_t footprint(const lj_index* idx, uint64_t m, uint64_t cap, Request* r) {
 }  // namespace
 
 // The batch on its slot's stream: the keys of host requests in; one fused
-// launch per kernel group for every request probed directly on a plain RMI
-// (their counts written by the kernel straight into the slot's pinned count
-// words), followed by one event that completes them all; then every other
-// request (binned probes, gapped and hash indexes, empty requests) with its
-// own probe, count copy and event, so that the completion thread can return
-// each request as soon as its own work is done.
+// launch per kernel group for every request probed directly on a plain or
+// gapped RMI (their counts written by the kernel straight into the slot's
+// pinned count words), followed by one event that completes them all; then
+// every other request (binned probes, learned hash indexes, exponential
+// search, empty requests) with its own probe, count copy and event, so that
+// the completion thread can return each request as soon as its own work is
+// done.
 hipError_t lj_server::enqueue_batch(Slot* s) {
     hipError_t e = hipSuccess;
     const size_t nb = s->batch.size();
@@ -184,7 +185,8 @@ hipError_t lj_server::enqueue_batch(Slot* s) {
         return grp[a] != grp[b] ? grp[a] < grp[b] : s->batch[a]->m > s->batch[b]->m;
     });
     if (!order.empty() && e == hipSuccess) {
-        lj::FusedJob* jobs_dev = (lj::FusedJob*)(s->fused_dev + 4 * lj::kFusedHeader);
+        lj::FusedJob* jobs_dev =
+            (lj::FusedJob*)(s->fused_dev + lj::kFusedGroups * lj::kFusedHeader);
         size_t a = 0;
         while (a < order.size()) {
             size_t z = a;
@@ -409,7 +411,7 @@ int lj_server_create(lj_index* const* indexes, uint32_t n, const lj_server_confi
             hipHostGetDevicePointer((void**)&s->counts_dev, s->counts_host, 0) != hipSuccess ||
             hipHostMalloc((void**)&s->jobs_host,
                           sizeof(lj::FusedJob) * cfg->max_batch_requests) != hipSuccess ||
-            hipMalloc((void**)&s->fused_dev, 4 * lj::kFusedHeader +
+            hipMalloc((void**)&s->fused_dev, lj::kFusedGroups * lj::kFusedHeader +
                                                  sizeof(lj::FusedJob) * cfg->max_batch_requests) !=
                 hipSuccess) {
             (void)hipGetLastError();

@@ -123,8 +123,9 @@ def test_autotune_then_plan():
 @pytest.mark.parametrize("kpl", [4, 8, 16, 24])
 def test_fused_plan_tile_shapes_and_many_batches(kpl):
     # Many small and ragged batches of every kernel group (FP32 / FP64
-    # leaves, unique / duplicate keys, linear and radix roots) in one fused
-    # plan; each size class with the given keys per lane (24 runs as 16).
+    # leaves, unique / duplicate keys, linear and radix roots, plain and
+    # gapped RMIs) in one fused plan; each size class with the given keys
+    # per lane (16 and 24 run as 8).
     import torch
     rng = np.random.default_rng(kpl)
     items = []
@@ -138,7 +139,10 @@ def test_fused_plan_tile_shapes_and_many_batches(kpl):
         S = workloads.gen.probe_mix(R, m, 0.5, 1000 + i, miss_hi=2**30)
         flags = (lj.LJ_LEAF_FP64 if i % 3 == 0 else lj.LJ_LEAF_FP32) | \
             (lj.LJ_ROOT_RADIX if i % 2 else 0)
-        ix = lj.lj_build_rmi(R, max(1, n // 200), flags)
+        if i % 7 in (3, 4):  # gapped RMIs (both leaf kinds, unique and duplicate keys)
+            ix = lj.lj_build_gapped_rmi(R, max(1, n // 200), 1 + i % 5, flags)
+        else:
+            ix = lj.lj_build_rmi(R, max(1, n // 200), flags)
         cap = max(1, m * int(ix.stats.max_mult))
         s = lj.to_device_keys(S)
         out = torch.full((cap, 2), -1, dtype=torch.int32, device="cuda")

@@ -16,10 +16,12 @@ pytestmark = pytest.mark.gpu
 
 def _indexes():
     ws = [workloads.c1_uniform(scale=0.2), workloads.c3_dup_runs(scale=0.002),
-          workloads.c2_lognormal_zipf(scale=0.001)]
+          workloads.c2_lognormal_zipf(scale=0.001), workloads.c2_lognormal_zipf(scale=0.002)]
     ixs = [lj.lj_build_rmi(w.R, w.leaves, (lj.LJ_LEAF_FP32 if i != 1 else lj.LJ_LEAF_FP64)
                            | (lj.LJ_ROOT_RADIX if i == 2 else 0))
-           for i, w in enumerate(ws)]
+           for i, w in enumerate(ws[:3])]
+    ixs.append(lj.lj_build_gapped_rmi(ws[3].R, ws[3].leaves, 4,
+                                      lj.LJ_LEAF_FP32 | lj.LJ_ROOT_RADIX))
     return ws, ixs
 
 
