@@ -319,13 +319,7 @@ def bench_sort_join(args) -> None:
     kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     ms_per_step = wall * 1e3 / args.steps
     latency = latency_reps(step, max(args.latency_reps, args.steps))
-    if args.copy_calibration_mib:
-        src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    copy_calibration(args)
     # Join kernel: per key of S its key (8 B) and partition number (4 B)
     # read, one 64 B sector of the sorted R searched, an 8 B result written.
     alg = 84.0 * m
@@ -371,6 +365,20 @@ def bench_sort_join(args) -> None:
 def root_flag(args) -> int:
     from paper_2111_08824_amd import lj
     return lj.LJ_ROOT_RADIX if args.root == "radix" else 0
+
+
+def copy_calibration(args) -> None:
+    """Three plain device copies of --copy-calibration-mib MiB after the
+    timed work: the reference that scales HBM byte counters."""
+    if not args.copy_calibration_mib:
+        return
+    import torch
+    src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def _json_line(res: dict) -> None:
@@ -454,14 +462,26 @@ def bench_multi_index(args) -> None:
     if got != expected:
         raise SystemExit("batched pair counts differ from the generator's hit counts")
     latency = latency_reps(plan_step, max(args.latency_reps, args.steps))
+    copy_calibration(args)
     value = m_total / (plan_ms * 1e-3)
     alg = sum(algorithmic_bytes(out, c, s.numel()) for (_, s, out, _), c in zip(batches, got))
     achieved = alg / (dev_ms * 1e-3) / 1e9
+    # HBM bytes of one replay from the committed counter summary, when it
+    # was taken on the current kernel sources and the plan is one fused
+    # launch (every index here is a plain FP32 RMI without duplicates, so
+    # a fused plan with no binned batch is one launch; the summary counts
+    # that launch's kernels).
+    one_launch = tuning.fused == 1 and tuning.binned_min_keys in (0, 2**64 - 1)
+    traffic = (_summary_value(os.path.join(ROOT, "profiles",
+                                           "batched_fused_multi-index-64_hbm_counters.md"),
+                              "traffic_bytes_per_launch")
+               if args.root == "radix" and one_launch else None)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "algorithmic_bytes_per_launch": alg,
             "kernel": "plan run (graph replay of every batch's probe kernels)",
             "kernel_ms": round(dev_ms, 4),
+            "traffic_gbs": round(traffic / (dev_ms * 1e-3) / 1e9, 1) if traffic else None,
             "frac_step": round(alg / (plan_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     if args.diagnostics:
         roof.update(random_roofline(value, alg / m_total, measure_bw_rand(stream)))
@@ -858,14 +878,7 @@ def bench_inlj(args) -> None:
     print(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms per step, timed kernel "
           f"{kern_ms:.3f} ms", file=sys.stderr, flush=True)
     latency = latency_reps(step, max(args.latency_reps, args.steps))
-
-    if args.copy_calibration_mib:
-        src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    copy_calibration(args)
 
     slot_bytes = 16 if gapped or hashed else 8
     # The method's compulsory bytes per step (8 B per outer key, the R
