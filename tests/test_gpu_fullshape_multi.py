@@ -9,8 +9,11 @@ element by element against the oracle.
     keys or more binned;
   * serving-8x50M: 8 resident indexes of 5e7 keys, 240 requests of
     256..4M keys (log-uniform) over them, half with host buffers and half
-    with device buffers, through the default served configuration and one
-    that probes requests of 2^20 keys or more binned.
+    with device buffers, through the default served configuration, one
+    that probes requests of 2^20 keys or more binned, and the default one
+    over gapped RMIs (4 slots per key) of the same relations.
+
+Indexes use the radix root and FP32 leaves, as the benchmark's do.
 
 Every inner relation here is duplicate-free, so P is given element by
 element by the oracle's equal_range (tests/exact_pairs.py).
@@ -31,7 +34,7 @@ def test_multi_index_64_full_shape():
     ws = workloads.multi_index_batches(k=64)
     items = []
     for w in ws:
-        ix = lj.lj_build_rmi(w.R, w.leaves, lj.LJ_LEAF_FP32)
+        ix = lj.lj_build_rmi(w.R, w.leaves, lj.LJ_LEAF_FP32 | lj.LJ_ROOT_RADIX)  # as benchmarked
         s = lj.to_device_keys(w.S)
         out = torch.empty((max(1, len(w.S)), 2), dtype=torch.int32, device="cuda")
         cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -68,7 +71,9 @@ def test_serving_8x50m_full_shape():
     import torch
     print("[fullshape] generating the 8 resident indexes", flush=True)
     ws = workloads.resident_indexes()
-    ixs = [lj.lj_build_rmi(w.R, w.leaves, lj.LJ_LEAF_FP32) for w in ws]
+    flags = lj.LJ_LEAF_FP32 | lj.LJ_ROOT_RADIX  # as the serving benchmark builds them
+    ixs = [lj.lj_build_rmi(w.R, w.leaves, flags) for w in ws]
+    gixs = [lj.lj_build_gapped_rmi(w.R, w.leaves, 4, flags) for w in ws]
     rng = np.random.default_rng(13)
     max_m = 4 << 20
     reqs = []
@@ -86,9 +91,10 @@ def test_serving_8x50m_full_shape():
     served = lj.lj_server_default_config(budget)
     binned = lj.lj_server_default_config(budget)
     binned.binned_min_keys = 1 << 20
-    for name, cfg in (("served", served), ("served, binned from 2^20", binned)):
+    for name, cfg, idx in (("served", served, ixs), ("served, binned from 2^20", binned, ixs),
+                           ("served, gapped RMIs", served, gixs)):
         print(f"[fullshape] server {name}", flush=True)
-        srv = lj.Server(ixs, cfg)
+        srv = lj.Server(idx, cfg)
         tickets, outs = [], []
         for i, a, m, dev in reqs:
             if dev:
