@@ -26,6 +26,8 @@
 // wave reads 16 runs of 64 consecutive keys.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lj_device.h"
 #include "lj_internal.h"
 
@@ -242,13 +244,19 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(T* __restrict__ d, uint64_
 // scanned digit-major counts of bin_hist_kernel for the same chunks.
 // keys_out[dest] = keys_in[p], bins_out[dest] = bins_in[p] (when bins_out is
 // given) and dest_out[p] = dest for every input position p.
+// kWriteBins: the pass also stores the bins in their new order (the first
+// pass, for the second); without it the LDS stage keeps only the 1-byte
+// digit (38 KB of LDS instead of 42 KB), which lets four workgroups share a
+// CU instead of three.
+template <bool kWriteBins>
 __global__ __launch_bounds__(kBlock) void bin_scatter_kernel(
     const uint64_t* __restrict__ keys_in, const uint16_t* __restrict__ bins_in,
     const uint32_t* __restrict__ gofs, uint64_t m, uint32_t nchunks, uint32_t shift,
     uint64_t* __restrict__ keys_out, uint16_t* __restrict__ bins_out,
     uint32_t* __restrict__ dest_out) {
+    using StageT = typename std::conditional<kWriteBins, uint16_t, uint8_t>::type;
     __shared__ uint64_t skey[kPartChunk];
-    __shared__ uint16_t sbin[kPartChunk];
+    __shared__ StageT sbin[kPartChunk];
     __shared__ uint32_t wbase[kWaves][kDigits];  // wave totals, then wave bases
     __shared__ uint32_t lstart[kDigits];         // chunk-local start of each digit
     __shared__ uint32_t gstart[kDigits];         // global start of each digit's run
@@ -311,18 +319,18 @@ __global__ __launch_bounds__(kBlock) void bin_scatter_kernel(
                 const uint32_t dg = digit_of(b[k], shift);
                 const uint32_t lpos = wbase[wave][dg] + rank[k];
                 skey[lpos] = x[k];
-                sbin[lpos] = (uint16_t)b[k];
+                sbin[lpos] = kWriteBins ? (StageT)b[k] : (StageT)dg;
                 dest_out[p] = gstart[dg] + (lpos - lstart[dg]);
             }
         }
         __syncthreads();
         const uint32_t nvalid = m - c0 < kPartChunk ? (uint32_t)(m - c0) : kPartChunk;
         for (uint32_t lp = tid; lp < nvalid; lp += kBlock) {
-            const uint32_t bin = sbin[lp];
-            const uint32_t dg = digit_of(bin, shift);
+            const uint32_t v = sbin[lp];
+            const uint32_t dg = kWriteBins ? digit_of(v, shift) : v;
             const uint32_t dst = gstart[dg] + (lp - lstart[dg]);
             keys_out[dst] = skey[lp];
-            if (bins_out) bins_out[dst] = (uint16_t)bin;
+            if constexpr (kWriteBins) bins_out[dst] = (uint16_t)v;
         }
         __syncthreads();
     }
@@ -430,8 +438,8 @@ hipError_t launch_partition(const lj_index* idx, const uint64_t* s, uint64_t m, 
                            0u, hist1);
     hipLaunchKernelGGL(scan_kernel<uint32_t>, dim3(scan_grid), dim3(kBlock), 0, stream, hist1,
                        nh, (uint64_t*)(w + L.scan_st1), ctr, err);
-    hipLaunchKernelGGL(bin_scatter_kernel, dim3(chunk_grid(nchunks, 65535)), dim3(kBlock), 0,
-                       stream, s, bins_s, hist1, m, nchunks, 0u, p1, bins_1,
+    hipLaunchKernelGGL(bin_scatter_kernel<true>, dim3(chunk_grid(nchunks, 65535)), dim3(kBlock),
+                       0, stream, s, bins_s, hist1, m, nchunks, 0u, p1, bins_1,
                        (uint32_t*)(w + L.dest1));
     // Pass 2: high digit.
     hipLaunchKernelGGL(bin_hist_kernel<false>, dim3(chunk_grid(nchunks, 4096)), dim3(kBlock), 0,
@@ -439,9 +447,9 @@ hipError_t launch_partition(const lj_index* idx, const uint64_t* s, uint64_t m, 
                        (const uint16_t*)nullptr, bins_1, m, nchunks, kDigitBits, hist2);
     hipLaunchKernelGGL(scan_kernel<uint32_t>, dim3(scan_grid), dim3(kBlock), 0, stream, hist2,
                        nh, (uint64_t*)(w + L.scan_st2), ctr + 1, err);
-    hipLaunchKernelGGL(bin_scatter_kernel, dim3(chunk_grid(nchunks, 65535)), dim3(kBlock), 0,
-                       stream, p1, bins_1, hist2, m, nchunks, kDigitBits, p2, (uint16_t*)nullptr,
-                       (uint32_t*)(w + L.dest2));
+    hipLaunchKernelGGL(bin_scatter_kernel<false>, dim3(chunk_grid(nchunks, 65535)), dim3(kBlock),
+                       0, stream, p1, bins_1, hist2, m, nchunks, kDigitBits, p2,
+                       (uint16_t*)nullptr, (uint32_t*)(w + L.dest2));
     return hipGetLastError();
 }
 
