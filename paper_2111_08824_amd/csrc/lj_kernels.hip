@@ -751,13 +751,14 @@ __device__ __forceinline__ void probe_join_body(const TileJob& j, uint32_t* tile
 }
 
 // The direct probe on a plain RMI (binary or exponential search of R) runs
-// at most three waves per SIMD: its keys miss every cache, and with more
-// resident waves the extra misses in flight only queue (measured on
-// lognormal-zipf-200M and the eight resident indexes of the serving
-// workload: 5-7% faster than the five waves its registers allow).  The
-// gapped and hash searches keep their full occupancy.
+// at most two waves per SIMD: its keys miss every cache, and with more
+// resident waves the extra misses in flight only queue and evict each
+// other's lines (measured on lognormal-zipf-200M: two or three waves are
+// 5-6% faster than the five its registers allow, and two read 1.90 L2->HBM
+// lines per key against 2.16 with three, at the same speed).  The gapped
+// and hash searches keep their full occupancy.
 template <class Leaf, bool kUnique, int kItems, int kSearch>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 3))) void
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 probe_join_kernel(TileJob j, uint32_t* tile_counter) {
     probe_join_body<Leaf, kUnique, kItems, kSearch>(j, tile_counter);
 }
@@ -1195,8 +1196,9 @@ __device__ __forceinline__ void fused_body(const FusedJob* __restrict__ jobs, ui
     }
 }
 
-// Plain RMIs at most three waves per SIMD, as probe_join_kernel; gapped
-// RMIs at full occupancy, as probe_join_slots_kernel.
+// Plain RMIs at most three waves per SIMD (a fused launch of many batches
+// measured 2% faster with three than with two); gapped RMIs at full
+// occupancy, as probe_join_slots_kernel.
 template <class Leaf, bool kUnique>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 3))) void
 probe_fused_kernel(const FusedJob* __restrict__ jobs, uint32_t njobs, uint32_t total_tiles,
