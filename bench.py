@@ -906,7 +906,8 @@ def bench_inlj(args) -> None:
             "kernel": (("probe_binned_gapped_kernel+gapped_queue_kernel"
                         if gapped and st.max_mult <= 1 else "probe_binned_kernel")
                        if binned else
-                       ("probe_join_slots_kernel" if gapped or hashed else "probe_join_kernel")),
+                       ("probe_join_full_kernel" if gapped or hashed or st.max_mult > 1
+                        else "probe_join_kernel")),
             "kernel_ms": round(kern_ms, 4),
             "traffic_gbs": round(traffic / (kern_ms * 1e-3) / 1e9, 1) if traffic else None,
             "step_algorithmic_bytes": step_alg,

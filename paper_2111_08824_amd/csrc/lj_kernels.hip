@@ -750,21 +750,23 @@ __device__ __forceinline__ void probe_join_body(const TileJob& j, uint32_t* tile
     probe_tile<Leaf, kUnique, kItems, !kUnique, kSearch>(j, s_root, s_tile, kItems, sh);
 }
 
-// The direct probe on a plain RMI (binary or exponential search of R) runs
-// at most two waves per SIMD: its keys miss every cache, and with more
-// resident waves the extra misses in flight only queue and evict each
-// other's lines (measured on lognormal-zipf-200M: two or three waves are
-// 5-6% faster than the five its registers allow, and two read 1.90 L2->HBM
-// lines per key against 2.16 with three, at the same speed).  The gapped
-// and hash searches keep their full occupancy.
+// The direct probe on a plain RMI without duplicate keys (binary or
+// exponential search of R) runs at most two waves per SIMD: its keys miss
+// every cache, and with more resident waves the extra misses in flight only
+// queue and evict each other's lines (measured on lognormal-zipf-200M: two
+// or three waves are 5-6% faster than the five its registers allow, and two
+// read 1.90 L2->HBM lines per key against 2.16 with three, at the same
+// speed).  probe_join_full_kernel keeps the full occupancy for the
+// duplicate-key probe (4 keys per lane: it needs every wave's loads in
+// flight; two waves cost it 17%) and for the gapped and hash searches.
 template <class Leaf, bool kUnique, int kItems, int kSearch>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 probe_join_kernel(TileJob j, uint32_t* tile_counter) {
     probe_join_body<Leaf, kUnique, kItems, kSearch>(j, tile_counter);
 }
 template <class Leaf, bool kUnique, int kItems, int kSearch>
-__global__ __launch_bounds__(kBlock) void probe_join_slots_kernel(TileJob j,
-                                                                  uint32_t* tile_counter) {
+__global__ __launch_bounds__(kBlock) void probe_join_full_kernel(TileJob j,
+                                                                 uint32_t* tile_counter) {
     probe_join_body<Leaf, kUnique, kItems, kSearch>(j, tile_counter);
 }
 
@@ -1198,7 +1200,7 @@ __device__ __forceinline__ void fused_body(const FusedJob* __restrict__ jobs, ui
 
 // Plain RMIs at most three waves per SIMD (a fused launch of many batches
 // measured 2% faster with three than with two); gapped RMIs at full
-// occupancy, as probe_join_slots_kernel.
+// occupancy, as probe_join_full_kernel.
 template <class Leaf, bool kUnique>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 3))) void
 probe_fused_kernel(const FusedJob* __restrict__ jobs, uint32_t njobs, uint32_t total_tiles,
@@ -1256,8 +1258,8 @@ namespace {
 template <class Leaf, bool kUnique, int kItems, int kSearch>
 hipError_t launch_join(const TileJob& j, uint32_t* ctr, hipStream_t stream) {
     const dim3 grid(j.ntiles), block(kBlock);
-    if constexpr (kSearch == kSearchGapped || kSearch == kSearchHash)
-        hipLaunchKernelGGL((probe_join_slots_kernel<Leaf, kUnique, kItems, kSearch>), grid,
+    if constexpr (!kUnique || kSearch == kSearchGapped || kSearch == kSearchHash)
+        hipLaunchKernelGGL((probe_join_full_kernel<Leaf, kUnique, kItems, kSearch>), grid,
                            block, 0, stream, j, ctr);
     else
         hipLaunchKernelGGL((probe_join_kernel<Leaf, kUnique, kItems, kSearch>), grid, block, 0,
